@@ -1,0 +1,8 @@
+"""Seeded synthetic traffic-tensor inputs shared by the oracle tests, the GPU tests and the bench.
+
+This package only draws input data (observed tensor, sampling mask, initial factors).
+It holds none of the completion method's arithmetic; see ``synth.traffic``.
+"""
+from .traffic import WORKLOADS, Workload, make_inputs, make_workload
+
+__all__ = ["WORKLOADS", "Workload", "make_inputs", "make_workload"]
