@@ -1,0 +1,162 @@
+/*
+ * tctf2r.h - C ABI of the MI355X (gfx950) TCTF2R completion library.
+ *
+ * TCTF2R is the separable low-tubal-rank completion method of Ling, Yu, Qi and Xu,
+ * "A Parallelizable Method for Missing Internet Traffic Tensor Data" (arXiv:2005.09838).
+ * Problem statement (section 3.1, eq. (TETP-optim)):
+ *
+ *   min  f0 = 1/2 ||X*Y - W||^2 + mu/2 ||W||^2
+ *             + rho1/2 ||H unfold(X*Y, 1)||^2 + rho2/2 ||K unfold(W, 2)||^2
+ *   s.t. P_Omega(W) = P_Omega(G),
+ *
+ * with X (n1 x r x n3), Y (r x n2 x n3), W (n1 x n2 x n3) real, "*" the t-product along
+ * mode 3, H and K the first-difference matrices of eq. (Toeplitz) along modes 1 and 2.
+ * One iteration (section 4.1, algorithm box, steps 1-4 and 7) transforms along the tube,
+ * updates every frequency's factors with pseudo-inverse-preconditioned block steps
+ * (eq. (updataXYW1)), transforms Z~ = X~Y~ back, solves the per-row W-step (eq. (Wkiom))
+ * and transforms W again.
+ *
+ * Conventions
+ *  - Every array pointer is a DEVICE pointer on the device that is current when
+ *    tctf_create is called (for instance a torch tensor's data_ptr()).
+ *  - Tensors are C-contiguous [n1][n2][n3] (mode 3 fastest): G, the mask, W.
+ *    X is [n1][r][n3] and Y is [r][n2][n3].
+ *  - The caller owns every buffer, including the workspace; the library never
+ *    allocates device memory and never frees caller memory.
+ *  - The tube transform uses the paper's root omega = exp(+2 pi i / n3) (eq. (bar BA-k)).
+ *  - A context belongs to one HIP stream and must be used from one host thread at a time.
+ *    Calls that return results synchronise that stream; tctf_step only enqueues work.
+ *  - Errors: every argument check runs before any device work; no call aborts or throws.
+ *    On failure a status below is returned and tctf_last_error() holds a detail string.
+ */
+#ifndef TCTF2R_H
+#define TCTF2R_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TCTF_OK = 0,
+  TCTF_E_ARG = -1,        /* NULL pointer or parameter out of range                    */
+  TCTF_E_SHAPE = -2,      /* sizes out of the supported range (see tctf_params)         */
+  TCTF_E_NONFINITE = -3,  /* an observed value of G is NaN/Inf, or the iterate became so */
+  TCTF_E_HIP = -4,        /* a HIP runtime call failed (detail in tctf_last_error())    */
+  TCTF_E_WORKSPACE = -5,  /* workspace NULL, too small or misaligned (256 B)            */
+  TCTF_E_STATE = -6       /* checkpoint blob of the wrong size or for another problem   */
+} tctf_status;
+
+typedef enum {
+  TCTF_FP32 = 0,        /* FP32 storage and products; the reduction over n1 of X~^* W~
+                           accumulates in FP64; r x r Grams, pseudo-inverses, objective FP64 */
+  TCTF_MIXED_BF16 = 1   /* W~ stored in BF16; the three slice products take BF16 operands
+                           with FP32 accumulation; factors, G and W stay FP32; r x r Grams,
+                           pseudo-inverses and objective FP64                                */
+} tctf_precision;
+
+typedef struct {
+  int32_t n1, n2, n3;   /* G is n1 x n2 x n3; n1, n2 >= 1; n3 in the supported set below    */
+  int32_t r;            /* tubal rank of the factorisation, 1 <= r <= min(n1, n2, 32)
+                           (section 3.1: X is n1 x r x n3, Y is r x n2 x n3)                */
+  double mu;            /* ridge weight on W (eq. (ETP-optim)), >= 0                       */
+  double rho1;          /* temporal-stability weight of H along mode 1 (eq. (TETP-optim)), >= 0 */
+  double rho2;          /* periodicity weight of K along mode 2 (eq. (TETP-optim)), >= 0   */
+  double eta;           /* common step alpha/L = beta/L of eq. (updataXYW1), 0 < eta < 2;
+                           1 gives the exact block minimiser                               */
+  int32_t precision;    /* tctf_precision                                                  */
+  int32_t pinv_mode;    /* 0: inverse by elimination when the Gram provably keeps every
+                           eigenvalue, eigen-decomposition otherwise; 1: always eigen     */
+  double eps;           /* threshold of the termination test (step 6), default 1e-6        */
+} tctf_params;
+/* Supported n3: 1..16, 20, 24, 28, 32, 40, 48, 56, 64, 84, 96, 112, 128 (the tube
+ * transform is generated for these lengths).  n2 <= 1024, n1 <= 65536. */
+
+typedef struct tctf_ctx tctf_ctx;
+
+/* Fill *p with defaults: mu = rho1 = rho2 = 1e-2, eta = 1, FP32, pinv_mode 0, eps = 1e-6.
+ * Sizes and r are set to 0 and must be filled in. */
+void tctf_default_params(tctf_params* p);
+
+/* Bytes of device workspace a context with these parameters needs (256-byte aligned). */
+tctf_status tctf_workspace_bytes(const tctf_params* p, size_t* bytes);
+
+/* Create a context (algorithm box, "Input" and "Initialize"; section 3.1 for P_Omega).
+ *  G      [n1][n2][n3] float, observed values; entries off Omega are ignored.
+ *  omega  [n1][n2][n3] uint8, nonzero = observed.
+ *  X0     [n1][r][n3] float or NULL (NULL = zeros).
+ *  Y0     [r][n2][n3] float or NULL (NULL = standard normal from a counter-based
+ *         generator keyed by seed).
+ *  W starts as P_Omega(G) (missing entries 0).  X0, Y0 are real, so the transformed
+ *  factors satisfy the conjugate symmetry eq. (rcm_3-k+2).
+ *  workspace: device memory of tctf_workspace_bytes() bytes, 256-byte aligned, owned by
+ *  the caller and used exclusively by this context until tctf_destroy.
+ *  hip_stream: the hipStream_t every call of this context runs on (NULL = default).
+ *  G, omega, X0, Y0 are copied into the workspace; they may be freed once this returns.
+ *  Returns TCTF_E_NONFINITE if an observed value of G is not finite. */
+tctf_status tctf_create(const tctf_params* p, const float* G, const uint8_t* omega,
+                        const float* X0, const float* Y0, uint64_t seed,
+                        void* workspace, size_t ws_bytes, void* hip_stream, tctf_ctx** out);
+
+/* Enqueue `iters` iterations (steps 1-4 and 7 of the algorithm box; step 5 keeps r,
+ * step 6 is tctf_termination).  Asynchronous and stream-ordered. */
+tctf_status tctf_step(tctf_ctx* c, int32_t iters);
+
+/* Synchronise and return f0 of eq. (TETP-optim) at the current iterate, accumulated in
+ * FP64 (the fit, ridge and K terms from the spatial W-step rows, the H term from the
+ * Fourier form eq. (fun-XYW)). */
+tctf_status tctf_objective(tctf_ctx* c, double* f0);
+
+/* Synchronise and return the step-6 quantities of the last iteration:
+ * out[0] = ||X~+ - X~||_inf, out[1] = ||Y~+ - Y~||_inf, out[2] = ||W+ - W||_F, and
+ * out[3] = 1 if all three are <= eps.  Needs at least one iteration since create. */
+tctf_status tctf_termination(tctf_ctx* c, double out[4]);
+
+/* Synchronise and return stationarity measures at the current iterate (Theorem ThKKT,
+ * eq. (AKKTstar)): out[0] = sqrt(sum_k ||grad_X h_k||^2 + ||grad_Y h_k||^2) /
+ * (||W~|| (||X~|| + ||Y~||)) over the full spectrum; out[1] = max over unobserved entries
+ * of |(W_k K_{mu rho2} - Z_k)_ij| / ||Z||_inf; out[2] = max over observed |W - G|. */
+tctf_status tctf_stationarity(tctf_ctx* c, double out[3]);
+
+/* Synchronise and copy results out (algorithm box, "Output").  Any pointer may be NULL.
+ *  W [n1][n2][n3]: the completed tensor W of the last W-step (observed entries equal G).
+ *  Z [n1][n2][n3]: X*Y of the current factors.
+ *  X [n1][r][n3], Y [r][n2][n3]: the factors in the spatial domain (eq. (barAAk)). */
+tctf_status tctf_get_result(tctf_ctx* c, float* W, float* Z, float* X, float* Y);
+
+/* Bytes of a checkpoint blob, and save / restore of the iterate (X~, Y~, W~, iteration
+ * count) to / from DEVICE memory.  Restoring continues bit-identically. */
+tctf_status tctf_state_bytes(tctf_ctx* c, size_t* bytes);
+tctf_status tctf_get_state(tctf_ctx* c, void* dst, size_t bytes);
+tctf_status tctf_set_state(tctf_ctx* c, const void* src, size_t bytes);
+
+/* Iterations run since create (or as restored). */
+tctf_status tctf_iterations(tctf_ctx* c, int64_t* iters);
+
+/* Destroy a context (the workspace stays the caller's).  NULL is a no-op. */
+void tctf_destroy(tctf_ctx* c);
+
+/* One call: create, run `iters` iterations, copy W out, f0 (may be NULL), destroy. */
+tctf_status tctf_complete(const tctf_params* p, const float* G, const uint8_t* omega,
+                          const float* X0, const float* Y0, uint64_t seed, int32_t iters,
+                          void* workspace, size_t ws_bytes, void* hip_stream,
+                          float* W_out, double* f0_out);
+
+/* Time one stage of the iteration: launch it `reps` times back to back on the context's
+ * stream between two HIP events and return the mean duration in microseconds.  Stages:
+ *   0 slice kernel (inverse tube transform, W-step, forward transform; the W~ stream)
+ *   1 Z~ = X~Y~ products        2 A = W~Y~^* products and the X right-hand side
+ *   3 tridiagonal H_rho1 solve  4 X~^* W~ and Gram partials     5 Y-step and Grams
+ *   6 one whole iteration
+ * Stages 0-5 recompute from the current state without advancing it (6 does advance). */
+tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* mean_us);
+
+const char* tctf_status_string(tctf_status s);
+const char* tctf_last_error(void);  /* thread-local detail of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCTF2R_H */

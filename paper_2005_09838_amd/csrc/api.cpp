@@ -1,0 +1,495 @@
+// C ABI of the TCTF2R library: argument checks, workspace carve-up, the iteration
+// schedule and result / checkpoint transfers.  Every computation runs in the HIP kernels
+// launched from here; this file only validates, lays out memory and enqueues work.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/tctf2r.h"
+#include "kernels.h"
+
+namespace tctf {
+size_t slice_lds_bytes(int n2, int n3);
+size_t ystep_lds_bytes(int r);
+void slice_set_attr(int n3, size_t lds);
+void ystep_set_attr(size_t lds);
+}  // namespace tctf
+
+using tctf::Plan;
+
+static thread_local std::string g_err;
+
+static tctf_status fail(tctf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(call)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(TCTF_E_HIP, "%s: %s", #call, hipGetErrorString(e_));    \
+  } while (0)
+
+static const uint64_t kStateMagic = 0x54435446324bULL;   // "TCTF2K"
+
+struct StateHeader {
+  uint64_t magic;
+  int32_t n1, n2, n3, r, precision, pad;
+  int64_t iters;
+  uint64_t reserved[4];
+};
+
+struct Layout {
+  size_t gp, wt, zt, xt, yt, rhs, bpart, spart, dpart, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
+      flag, scal, xt_prev, yt_prev, wt_prev, stat_work, kkt, total;
+  size_t state_bytes;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static void chunking(int n1, int nb, int* nchunk, int* chunk) {
+  // aim at >= 512 blocks for the X~^* W~ reduction, rows per chunk a multiple of 16
+  int want = (512 + nb - 1) / nb;
+  int maxc = (n1 + 31) / 32;
+  int nc = want < maxc ? want : maxc;
+  const int minc = (n1 + 191) / 192;   // at most 192 rows per chunk (LDS of the Gram partials)
+  if (nc < minc) nc = minc;
+  if (nc < 1) nc = 1;
+  int ch = (n1 + nc - 1) / nc;
+  ch = ((ch + 15) / 16) * 16;
+  nc = (n1 + ch - 1) / ch;
+  *nchunk = nc;
+  *chunk = ch;
+}
+
+static Layout make_layout(const tctf_params& p) {
+  Layout L;
+  const size_t n1 = p.n1, n2 = p.n2, n3 = p.n3, r = p.r, nb = n3 / 2 + 1;
+  int nchunk, chunk;
+  chunking(p.n1, (int)nb, &nchunk, &chunk);
+  const size_t welem = p.precision == TCTF_MIXED_BF16 ? 4 : 8;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+  L.gp = take(n1 * n2 * n3 * 4);
+  L.wt = take(n1 * nb * n2 * welem);
+  L.zt = take(n1 * nb * n2 * 8);
+  L.xt = take(nb * r * n1 * 8);
+  L.yt = take(nb * r * n2 * 8);
+  L.rhs = take(nb * r * n1 * 8);
+  L.bpart = take(nb * nchunk * r * n2 * 8);
+  L.spart = take(nb * nchunk * r * r * 16);
+  L.dpart = take(nb * nchunk * r * r * 16);
+  L.gyp = take(nb * r * r * 16);
+  L.qy = take(nb * r * r * 16);
+  L.qy_zero = take(nb * 4);
+  L.slice_obj = take(n1 * 3 * 8);
+  L.bin_obj = take(nb * 8);
+  L.wtab = take(4 * n2 * 4);
+  L.htab = take(3 * n1 * 4);
+  L.flag = take(64);
+  L.scal = take(16 * 8);
+  L.xt_prev = take(nb * r * n1 * 8);
+  L.yt_prev = take(nb * r * n2 * 8);
+  L.wt_prev = take(n1 * nb * n2 * welem);
+  L.stat_work = take((nb * 8 + 256) * 8);
+  L.kkt = take(n1 * 3 * 8);
+  L.total = o;
+  L.state_bytes = sizeof(StateHeader) + nb * r * n1 * 8 + nb * r * n2 * 8 + n1 * nb * n2 * welem +
+                  2 * nb * r * r * 16 + nb * 4 + n1 * 3 * 8 + nb * 8;
+  return L;
+}
+
+struct tctf_ctx {
+  tctf_params prm;
+  Plan plan;
+  Layout lay;
+  unsigned char* ws;
+  int device;
+  int64_t iters;
+  bool term_valid;
+};
+
+static tctf_status validate(const tctf_params* p) {
+  if (!p) return fail(TCTF_E_ARG, "params is NULL");
+  if (p->n1 < 1 || p->n2 < 1 || p->n3 < 1) return fail(TCTF_E_SHAPE, "sizes must be >= 1 (got %d x %d x %d)", p->n1, p->n2, p->n3);
+  if (p->r < 1 || p->r > TCTF_RMAX || p->r > p->n1 || p->r > p->n2)
+    return fail(TCTF_E_SHAPE, "rank r=%d must satisfy 1 <= r <= min(n1, n2, %d)", p->r, TCTF_RMAX);
+  if (p->n1 > TCTF_N1MAX) return fail(TCTF_E_SHAPE, "n1=%d exceeds %d", p->n1, TCTF_N1MAX);
+  if (p->n2 > TCTF_N2MAX) return fail(TCTF_E_SHAPE, "n2=%d exceeds %d", p->n2, TCTF_N2MAX);
+  if (!tctf::slice_supported(p->n3)) return fail(TCTF_E_SHAPE, "n3=%d is not a supported tube length", p->n3);
+  if (tctf::slice_lds_bytes(p->n2, p->n3) > TCTF_SLICE_LDS_MAX)
+    return fail(TCTF_E_SHAPE, "n2 x (n3 + 1) = %d x %d does not fit the slice kernel's LDS", p->n2, p->n3 + 1);
+  if (!(std::isfinite(p->mu) && p->mu >= 0) || !(std::isfinite(p->rho1) && p->rho1 >= 0) ||
+      !(std::isfinite(p->rho2) && p->rho2 >= 0))
+    return fail(TCTF_E_ARG, "mu, rho1, rho2 must be finite and >= 0");
+  if (!(p->eta > 0.0 && p->eta < 2.0)) return fail(TCTF_E_ARG, "eta=%g must lie in (0, 2)", p->eta);
+  if (p->precision != TCTF_FP32 && p->precision != TCTF_MIXED_BF16) return fail(TCTF_E_ARG, "unknown precision %d", p->precision);
+  if (p->pinv_mode != 0 && p->pinv_mode != 1) return fail(TCTF_E_ARG, "pinv_mode must be 0 or 1");
+  if (!(p->eps >= 0.0)) return fail(TCTF_E_ARG, "eps must be >= 0");
+  return TCTF_OK;
+}
+
+extern "C" {
+
+void tctf_default_params(tctf_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->mu = 1e-2;
+  p->rho1 = 1e-2;
+  p->rho2 = 1e-2;
+  p->eta = 1.0;
+  p->precision = TCTF_FP32;
+  p->pinv_mode = 0;
+  p->eps = 1e-6;
+}
+
+tctf_status tctf_workspace_bytes(const tctf_params* p, size_t* bytes) {
+  tctf_status s = validate(p);
+  if (s != TCTF_OK) return s;
+  if (!bytes) return fail(TCTF_E_ARG, "bytes is NULL");
+  *bytes = make_layout(*p).total;
+  return TCTF_OK;
+}
+
+static void fill_plan(tctf_ctx* c, hipStream_t stream) {
+  const tctf_params& p = c->prm;
+  Plan& q = c->plan;
+  const Layout& L = c->lay;
+  unsigned char* w = c->ws;
+  q.n1 = p.n1;
+  q.n2 = p.n2;
+  q.n3 = p.n3;
+  q.r = p.r;
+  q.nb = p.n3 / 2 + 1;
+  chunking(p.n1, q.nb, &q.nchunk, &q.chunk);
+  q.mu = p.mu;
+  q.rho1 = p.rho1;
+  q.rho2 = p.rho2;
+  q.eta = p.eta;
+  q.mixed = p.precision == TCTF_MIXED_BF16;
+  q.force_eigen = p.pinv_mode == 1;
+  q.stream = stream;
+  q.gp = (float*)(w + L.gp);
+  q.wt = (void*)(w + L.wt);
+  q.zt = (float2*)(w + L.zt);
+  q.xt = (float2*)(w + L.xt);
+  q.yt = (float2*)(w + L.yt);
+  q.rhs = (float2*)(w + L.rhs);
+  q.bpart = (float2*)(w + L.bpart);
+  q.spart = (cd*)(w + L.spart);
+  q.dpart = (cd*)(w + L.dpart);
+  q.gyp = (cd*)(w + L.gyp);
+  q.qy = (cd*)(w + L.qy);
+  q.qy_zero = (int*)(w + L.qy_zero);
+  q.slice_obj = (double*)(w + L.slice_obj);
+  q.bin_obj = (double*)(w + L.bin_obj);
+  q.wtab = (float*)(w + L.wtab);
+  q.htab = (float*)(w + L.htab);
+  q.flag = (int*)(w + L.flag);
+  q.scal = (double*)(w + L.scal);
+  q.xt_prev = (float2*)(w + L.xt_prev);
+  q.yt_prev = (float2*)(w + L.yt_prev);
+  q.wt_prev = (void*)(w + L.wt_prev);
+  q.stat_work = (double*)(w + L.stat_work);
+  q.kkt = (double*)(w + L.kkt);
+}
+
+static tctf_status check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(TCTF_E_HIP, "kernel launch: %s", hipGetErrorString(e));
+  return TCTF_OK;
+}
+
+static tctf_status enqueue_iteration(tctf_ctx* c) {
+  const Plan& p = c->plan;
+  tctf::launch_agemm(p);
+  tctf::launch_hsolve(p);
+  tctf::launch_bgemm(p);
+  tctf::launch_ystep(p, 0);
+  tctf::launch_zgemm(p);
+  tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0);
+  return check_launch();
+}
+
+tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* omega, const float* X0,
+                        const float* Y0, uint64_t seed, void* workspace, size_t ws_bytes, void* hip_stream,
+                        tctf_ctx** out) {
+  tctf_status s = validate(prm);
+  if (s != TCTF_OK) return s;
+  if (!out) return fail(TCTF_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!G || !omega) return fail(TCTF_E_ARG, "G and omega must be device pointers");
+  const Layout L = make_layout(*prm);
+  if (!workspace) return fail(TCTF_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace & 255u) != 0) return fail(TCTF_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(TCTF_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+  tctf_ctx* c = new (std::nothrow) tctf_ctx();
+  if (!c) return fail(TCTF_E_ARG, "out of host memory");
+  c->prm = *prm;
+  c->lay = L;
+  c->ws = (unsigned char*)workspace;
+  c->iters = 0;
+  c->term_valid = false;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(TCTF_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  }
+  fill_plan(c, (hipStream_t)hip_stream);
+  const Plan& p = c->plan;
+  tctf::slice_set_attr(p.n3, tctf::slice_lds_bytes(p.n2, p.n3));
+  tctf::ystep_set_attr(tctf::ystep_lds_bytes(p.r));
+  tctf::launch_zero(p, p.flag, 64);
+  tctf::launch_zero(p, p.qy_zero, (size_t)p.nb * 4);
+  tctf::launch_pack_g(p, G, omega);
+  tctf::launch_tables(p);
+  if (X0) tctf::launch_tube_dft_setup(p, X0, p.xt, p.n1, p.r, (long)p.r * p.n1, 1, p.n1);
+  else tctf::launch_zero(p, p.xt, (size_t)p.nb * p.r * p.n1 * 8);
+  const float* y0 = Y0;
+  if (!y0) {
+    tctf::launch_normal(p, (float*)p.zt, (size_t)p.r * p.n2 * p.n3, seed);
+    y0 = (const float*)p.zt;
+  }
+  tctf::launch_tube_dft_setup(p, y0, p.yt, p.r, p.n2, (long)p.r * p.n2, p.n2, 1);
+  tctf::launch_zgemm(p);
+  tctf::launch_slice(p, tctf::SLICE_INIT, nullptr, nullptr, 1);
+  tctf::launch_bgemm(p);
+  tctf::launch_ystep(p, 1);
+  s = check_launch();
+  if (s != TCTF_OK) { delete c; return s; }
+  int flag = 0;
+  e = hipMemcpyAsync(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost, p.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(TCTF_E_HIP, "create: %s", hipGetErrorString(e));
+  }
+  if (flag) {
+    delete c;
+    return fail(TCTF_E_NONFINITE, "an observed value of G is NaN or Inf");
+  }
+  *out = c;
+  return TCTF_OK;
+}
+
+tctf_status tctf_step(tctf_ctx* c, int32_t iters) {
+  if (!c) return fail(TCTF_E_ARG, "context is NULL");
+  if (iters < 0) return fail(TCTF_E_ARG, "iters must be >= 0");
+  const Plan& p = c->plan;
+  for (int32_t it = 0; it < iters; ++it) {
+    if (it == iters - 1) {
+      const size_t welem = tctf::wt_elem_bytes(p);
+      HIP_TRY(hipMemcpyAsync(p.xt_prev, p.xt, (size_t)p.nb * p.r * p.n1 * 8, hipMemcpyDeviceToDevice, p.stream));
+      HIP_TRY(hipMemcpyAsync(p.yt_prev, p.yt, (size_t)p.nb * p.r * p.n2 * 8, hipMemcpyDeviceToDevice, p.stream));
+      HIP_TRY(hipMemcpyAsync(p.wt_prev, p.wt, (size_t)p.n1 * p.nb * p.n2 * welem, hipMemcpyDeviceToDevice, p.stream));
+    }
+    tctf_status s = enqueue_iteration(c);
+    if (s != TCTF_OK) return s;
+    c->iters++;
+  }
+  if (iters > 0) {
+    tctf::launch_termination(p);
+    c->term_valid = true;
+  }
+  return check_launch();
+}
+
+static tctf_status read_scalars(tctf_ctx* c, int first, int count, double* dst) {
+  const Plan& p = c->plan;
+  HIP_TRY(hipMemcpyAsync(dst, p.scal + first, count * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  return TCTF_OK;
+}
+
+tctf_status tctf_objective(tctf_ctx* c, double* f0) {
+  if (!c || !f0) return fail(TCTF_E_ARG, "NULL argument");
+  tctf::launch_objective(c->plan);
+  tctf_status s = check_launch();
+  if (s != TCTF_OK) return s;
+  s = read_scalars(c, 0, 1, f0);
+  if (s != TCTF_OK) return s;
+  if (!std::isfinite(*f0)) return fail(TCTF_E_NONFINITE, "objective is not finite");
+  return TCTF_OK;
+}
+
+tctf_status tctf_termination(tctf_ctx* c, double out[4]) {
+  if (!c || !out) return fail(TCTF_E_ARG, "NULL argument");
+  if (!c->term_valid) return fail(TCTF_E_STATE, "no iteration has run since create or restore");
+  tctf_status s = read_scalars(c, 4, 3, out);
+  if (s != TCTF_OK) return s;
+  const double eps = c->prm.eps;
+  out[3] = (out[0] <= eps && out[1] <= eps && out[2] <= eps) ? 1.0 : 0.0;
+  return TCTF_OK;
+}
+
+tctf_status tctf_stationarity(tctf_ctx* c, double out[3]) {
+  if (!c || !out) return fail(TCTF_E_ARG, "NULL argument");
+  tctf::launch_stationarity(c->plan, c->iters == 0 ? 1 : 0);
+  tctf_status s = check_launch();
+  if (s != TCTF_OK) return s;
+  return read_scalars(c, 8, 3, out);
+}
+
+tctf_status tctf_get_result(tctf_ctx* c, float* W, float* Z, float* X, float* Y) {
+  if (!c) return fail(TCTF_E_ARG, "context is NULL");
+  const Plan& p = c->plan;
+  if (W || Z) {
+    tctf::launch_zgemm(p);
+    tctf::launch_slice(p, tctf::SLICE_RESULT, W, Z, c->iters == 0 ? 1 : 0);
+  }
+  if (X) tctf::launch_tube_idft_setup(p, p.xt, X, p.n1, p.r, (long)p.r * p.n1, 1, p.n1);
+  if (Y) tctf::launch_tube_idft_setup(p, p.yt, Y, p.r, p.n2, (long)p.r * p.n2, p.n2, 1);
+  tctf_status s = check_launch();
+  if (s != TCTF_OK) return s;
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  return TCTF_OK;
+}
+
+// checkpoint blob: header, X~, Y~, W~, G_Y^+, I - eta P_Y, flags, objective partials
+struct Region { size_t off; size_t bytes; };
+
+static int state_regions(tctf_ctx* c, Region* r) {
+  const Plan& p = c->plan;
+  const Layout& L = c->lay;
+  const size_t welem = tctf::wt_elem_bytes(p);
+  int n = 0;
+  r[n++] = {L.xt, (size_t)p.nb * p.r * p.n1 * 8};
+  r[n++] = {L.yt, (size_t)p.nb * p.r * p.n2 * 8};
+  r[n++] = {L.wt, (size_t)p.n1 * p.nb * p.n2 * welem};
+  r[n++] = {L.gyp, (size_t)p.nb * p.r * p.r * 16};
+  r[n++] = {L.qy, (size_t)p.nb * p.r * p.r * 16};
+  r[n++] = {L.qy_zero, (size_t)p.nb * 4};
+  r[n++] = {L.slice_obj, (size_t)p.n1 * 3 * 8};
+  r[n++] = {L.bin_obj, (size_t)p.nb * 8};
+  return n;
+}
+
+tctf_status tctf_state_bytes(tctf_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(TCTF_E_ARG, "NULL argument");
+  *bytes = c->lay.state_bytes;
+  return TCTF_OK;
+}
+
+tctf_status tctf_get_state(tctf_ctx* c, void* dst, size_t bytes) {
+  if (!c || !dst) return fail(TCTF_E_ARG, "NULL argument");
+  if (bytes < c->lay.state_bytes) return fail(TCTF_E_STATE, "state buffer has %zu bytes, %zu needed", bytes, c->lay.state_bytes);
+  const Plan& p = c->plan;
+  StateHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.magic = kStateMagic;
+  h.n1 = p.n1; h.n2 = p.n2; h.n3 = p.n3; h.r = p.r; h.precision = c->prm.precision;
+  h.iters = c->iters;
+  unsigned char* d = (unsigned char*)dst;
+  HIP_TRY(hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, p.stream));
+  size_t off = sizeof(h);
+  Region reg[16];
+  const int n = state_regions(c, reg);
+  for (int k = 0; k < n; ++k) {
+    HIP_TRY(hipMemcpyAsync(d + off, c->ws + reg[k].off, reg[k].bytes, hipMemcpyDeviceToDevice, p.stream));
+    off += reg[k].bytes;
+  }
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  return TCTF_OK;
+}
+
+tctf_status tctf_set_state(tctf_ctx* c, const void* src, size_t bytes) {
+  if (!c || !src) return fail(TCTF_E_ARG, "NULL argument");
+  if (bytes < c->lay.state_bytes) return fail(TCTF_E_STATE, "state blob has %zu bytes, %zu needed", bytes, c->lay.state_bytes);
+  const Plan& p = c->plan;
+  StateHeader h;
+  const unsigned char* s = (const unsigned char*)src;
+  HIP_TRY(hipMemcpyAsync(&h, s, sizeof(h), hipMemcpyDeviceToHost, p.stream));
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  if (h.magic != kStateMagic || h.n1 != p.n1 || h.n2 != p.n2 || h.n3 != p.n3 || h.r != p.r ||
+      h.precision != c->prm.precision)
+    return fail(TCTF_E_STATE, "state blob belongs to another problem");
+  size_t off = sizeof(h);
+  Region reg[16];
+  const int n = state_regions(c, reg);
+  for (int k = 0; k < n; ++k) {
+    HIP_TRY(hipMemcpyAsync(c->ws + reg[k].off, s + off, reg[k].bytes, hipMemcpyDeviceToDevice, p.stream));
+    off += reg[k].bytes;
+  }
+  HIP_TRY(hipStreamSynchronize(p.stream));
+  c->iters = h.iters;
+  c->term_valid = false;
+  return TCTF_OK;
+}
+
+tctf_status tctf_iterations(tctf_ctx* c, int64_t* iters) {
+  if (!c || !iters) return fail(TCTF_E_ARG, "NULL argument");
+  *iters = c->iters;
+  return TCTF_OK;
+}
+
+void tctf_destroy(tctf_ctx* c) { delete c; }
+
+tctf_status tctf_complete(const tctf_params* p, const float* G, const uint8_t* omega, const float* X0,
+                          const float* Y0, uint64_t seed, int32_t iters, void* workspace, size_t ws_bytes,
+                          void* hip_stream, float* W_out, double* f0_out) {
+  if (!W_out) return fail(TCTF_E_ARG, "W_out is NULL");
+  tctf_ctx* c = nullptr;
+  tctf_status s = tctf_create(p, G, omega, X0, Y0, seed, workspace, ws_bytes, hip_stream, &c);
+  if (s != TCTF_OK) return s;
+  s = tctf_step(c, iters);
+  if (s == TCTF_OK) s = tctf_get_result(c, W_out, nullptr, nullptr, nullptr);
+  if (s == TCTF_OK && f0_out) s = tctf_objective(c, f0_out);
+  tctf_destroy(c);
+  return s;
+}
+
+tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* mean_us) {
+  if (!c || !mean_us) return fail(TCTF_E_ARG, "NULL argument");
+  if (stage < 0 || stage > 6 || reps < 1) return fail(TCTF_E_ARG, "stage must be 0..6 and reps >= 1");
+  const Plan& p = c->plan;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, p.stream));
+  for (int k = 0; k < reps; ++k) {
+    switch (stage) {
+      case 0: tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0); break;
+      case 1: tctf::launch_zgemm(p); break;
+      case 2: tctf::launch_agemm(p); break;
+      case 3: tctf::launch_hsolve(p); break;
+      case 4: tctf::launch_bgemm(p); break;
+      case 5: tctf::launch_ystep(p, 1); break;
+      case 6: enqueue_iteration(c); c->iters++; break;
+    }
+  }
+  HIP_TRY(hipEventRecord(e1, p.stream));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *mean_us = 1000.0 * ms / reps;
+  return check_launch();
+}
+
+const char* tctf_status_string(tctf_status s) {
+  switch (s) {
+    case TCTF_OK: return "ok";
+    case TCTF_E_ARG: return "invalid argument";
+    case TCTF_E_SHAPE: return "unsupported shape";
+    case TCTF_E_NONFINITE: return "non-finite value";
+    case TCTF_E_HIP: return "HIP runtime error";
+    case TCTF_E_WORKSPACE: return "bad workspace";
+    case TCTF_E_STATE: return "bad state";
+  }
+  return "unknown status";
+}
+
+const char* tctf_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Kernel launchers of the TCTF2R gfx950 library (host-callable, stream-ordered).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "common.h"
+
+namespace tctf {
+
+// Device buffers and sizes of one completion (carved from the caller's workspace).
+struct Plan {
+  int n1, n2, n3, r, nb;       // nb = n3/2 + 1 stored frequencies
+  int nchunk, chunk;           // row chunks of the X~^* W~ reduction
+  double mu, rho1, rho2, eta;
+  int mixed, force_eigen;
+  hipStream_t stream;
+
+  float* gp;        // [n1][n2][n3] observed values; unobserved entries NaN-coded (run position)
+  void* wt;         // W~ [n1][nb][n2] float2 (FP32) or packed bf16x2 (mixed)
+  float2* zt;       // Z~ [n1][nb][n2]
+  float2* xt;       // X~ [nb][r][n1]
+  float2* yt;       // Y~ [nb][r][n2]
+  float2* rhs;      // right-hand side of the H_rho1 solve [nb][r][n1]
+  float2* bpart;    // partial X~^* W~ [nb][nchunk][r][n2]
+  cd* spart;        // partial X~^* X~  [nb][nchunk][r][r]
+  cd* dpart;        // partial (H X~)^* (H X~) [nb][nchunk][r][r]
+  cd* gyp;          // (Y~ Y~^*)^+ [nb][r][r]
+  cd* qy;           // I - eta P_Y [nb][r][r]
+  int* qy_zero;     // [nb] 1 when I - eta P_Y is exactly 0 (eta = 1, full rank)
+  double* slice_obj;// [n1][3] fit, ridge and mode-2 difference sums of the last W-step
+  double* bin_obj;  // [nb] c_b tr((H X~_b)^*(H X~_b) Y~_b Y~_b^*)
+  float* wtab;      // [4][n2] reciprocal pivots of the W-step row systems
+  float* htab;      // [3][n1] Thomas coefficients of H_rho1
+  int* flag;        // non-finite detector
+  double* scal;     // [16] scalar results (objective, termination, stationarity)
+  float2* xt_prev;  // snapshots for the termination test
+  float2* yt_prev;
+  void* wt_prev;
+  double* stat_work;// [nb][8] stationarity partial sums (and termination partials)
+  double* kkt;      // [n1][3] W-KKT residual maxima of the slices
+};
+
+size_t wt_elem_bytes(const Plan& p);
+
+// setup
+void launch_pack_g(const Plan& p, const float* G, const uint8_t* omega);
+void launch_tables(const Plan& p);
+void launch_tube_dft_setup(const Plan& p, const float* src, float2* dst, int P, int Q,
+                           long sb, long sp, long sq);   // real [P][Q][n3] -> half spectrum
+void launch_tube_idft_setup(const Plan& p, const float2* src, float* dst, int P, int Q,
+                            long sb, long sp, long sq);  // half spectrum -> real [P][Q][n3]
+void launch_normal(const Plan& p, float* dst, size_t n, uint64_t seed);
+void launch_zero(const Plan& p, void* dst, size_t bytes);
+
+// iteration
+enum SliceMode { SLICE_INIT = 0, SLICE_ITER = 1, SLICE_RESULT = 2, SLICE_KKT = 3 };
+bool slice_supported(int n3);
+void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g);
+void launch_zgemm(const Plan& p);
+void launch_agemm(const Plan& p, int raw_a = 0);
+void launch_hsolve(const Plan& p);
+void launch_bgemm(const Plan& p);
+void launch_ystep(const Plan& p, int init);
+void launch_objective(const Plan& p);
+void launch_termination(const Plan& p);
+void launch_stationarity(const Plan& p, int w_from_g);
+
+}  // namespace tctf

@@ -1,0 +1,96 @@
+"""C ABI behaviour on the GPU: error statuses, NaN detection, workspace checks, mixed precision."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import gpu_run, make_inputs, make_workload, oracle, oracle_run, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(n1, n2, n3, r, **kw):
+    from paper_2005_09838_amd import make_params
+    return make_params(n1, n2, n3, r, **kw)
+
+
+def test_nonfinite_observation_is_reported():
+    import torch
+    from paper_2005_09838_amd import binding as B
+    d = make_inputs(10, 8, 4, 2, p=0.5, seed=1)
+    g = d["G"].copy()
+    idx = np.argwhere(d["omega"] == 1)[0]
+    g[tuple(idx)] = np.nan
+    p = _params(10, 8, 4, 2)
+    n = B.tctf_workspace_bytes(p)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(B.TctfError) as e:
+        B.tctf_create(p, to_dev(g), to_dev(d["omega"]), None, to_dev(d["Y0"]), 0, ws, n, None)
+    assert e.value.status == B.TCTF_E_NONFINITE
+    # a NaN off Omega is ignored
+    g2 = d["G"].copy()
+    idx = np.argwhere(d["omega"] == 0)[0]
+    g2[tuple(idx)] = np.nan
+    ctx = B.tctf_create(p, to_dev(g2), to_dev(d["omega"]), None, to_dev(d["Y0"]), 0, ws, n, None)
+    B.tctf_step(ctx, 2)
+    assert np.isfinite(B.tctf_objective(ctx))
+    B.tctf_destroy(ctx)
+
+
+def test_workspace_and_argument_errors():
+    import torch
+    from paper_2005_09838_amd import binding as B
+    d = make_inputs(10, 8, 4, 2, p=0.5, seed=1)
+    p = _params(10, 8, 4, 2)
+    n = B.tctf_workspace_bytes(p)
+    ws = torch.empty(n + 512, dtype=torch.uint8, device="cuda:0")
+    G, om = to_dev(d["G"]), to_dev(d["omega"])
+    with pytest.raises(B.TctfError) as e:
+        B.tctf_create(p, G, om, None, None, 0, ws, n - 1, None)
+    assert e.value.status == B.TCTF_E_WORKSPACE
+    with pytest.raises(B.TctfError) as e:
+        B.tctf_create(p, G, om, None, None, 0, ws.data_ptr() + 4, n, None)
+    assert e.value.status == B.TCTF_E_WORKSPACE
+    with pytest.raises(B.TctfError) as e:
+        B.tctf_create(p, None, om, None, None, 0, ws, n, None)
+    assert e.value.status == B.TCTF_E_ARG
+    ctx = B.tctf_create(p, G, om, None, None, 0, ws, n, None)
+    with pytest.raises(B.TctfError) as e:
+        B.tctf_termination(ctx)
+    assert e.value.status == B.TCTF_E_STATE
+    with pytest.raises(B.TctfError) as e:
+        B.tctf_step(ctx, -1)
+    assert e.value.status == B.TCTF_E_ARG
+    small = torch.empty(16, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(B.TctfError) as e:
+        B.tctf_set_state(ctx, small, 16)
+    assert e.value.status == B.TCTF_E_STATE
+    B.tctf_destroy(ctx)
+
+
+def test_complete_one_call():
+    import torch
+    from paper_2005_09838_amd import binding as B
+    w, d = make_workload("od36x48x7_r3")
+    p = _params(36, 48, 7, 3)
+    n = B.tctf_workspace_bytes(p)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    W = torch.empty((36, 48, 7), dtype=torch.float32, device="cuda:0")
+    f0 = B.tctf_complete(p, to_dev(d["G"]), to_dev(d["omega"]), to_dev(d["X0"]), to_dev(d["Y0"]), 0, 10, ws, n,
+                         None, W)
+    st, info = oracle_run(d, 3, 10, history=True)
+    assert rel(W.cpu().numpy(), st.w) < 1e-5
+    assert abs(f0 - info["f0"][-1]) / info["f0"][-1] < 1e-5
+
+
+def test_mixed_precision_tracks_fp32():
+    """BF16 storage of W~ and BF16 slice-product operands: the completion error stays close
+    to the FP32 path (reported in detail by the bench's equal-error protocol)."""
+    w, d = make_workload("od36x48x7_r3")
+    a = gpu_run(d, w.r, w.iters)
+    b = gpu_run(d, w.r, w.iters, precision="mixed")
+    rse_a = oracle.rse(a["W"], d["M"])
+    rse_b = oracle.rse(b["W"], d["M"])
+    print(f"RSE fp32 {rse_a:.5f} mixed {rse_b:.5f} W rel diff {rel(b['W'], a['W']):.2e}", flush=True)
+    assert np.all(np.isfinite(b["W"]))
+    assert abs(rse_b - rse_a) <= 0.05 * rse_a
