@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the TCTF2R iteration on one MI355X at 529 x 96 x 112, r = 16.
+
+A "step" is one full iteration of the method (X-step, Y-step, Z = X*Y, W-step and the
+tube transforms) over the synthetic 529 OD x 96 slot x 112 day traffic tensor (40 %
+sampled), with every input resident in device memory.  Both precisions are run:
+FP32 and mixed (BF16 W~ storage and BF16 slice-product operands, FP32 accumulation, FP64
+r x r Grams / pseudo-inverses / objective).  The equal-error protocol compares their
+completion error (RSE against the full synthetic tensor): FP32 after 200 iterations sets
+RSE32, and the mixed run's first iteration with RSE <= RSE32 (1 + 5e-3) is reported.
+
+Prints ONE JSON line (metric, value = iterations/s of the headline precision, the
+roofline of the dominant kernel, the FP64 CPU oracle baseline, per-precision details).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "od529x96x112_r16"
+PEAK_HBM_GBPS = 8000.0
+
+
+def algorithmic_bytes(n1, n2, n3, r, mixed):
+    """Bytes one iteration must move at minimum: read G once (FP32, unobserved entries
+    coded in the same word), write W~ once and read it once (for X~^* W~; A = W~ Y~^* is
+    formed where W~ is produced), and read / write the factors (5 |X~| + 4 |Y~|)."""
+    nb = n3 // 2 + 1
+    n = n1 * n2 * n3
+    nh = n1 * n2 * nb
+    sw = 4 if mixed else 8
+    fx, fy = 8 * nb * r * n1, 8 * nb * r * n2
+    return 4 * n + 2 * sw * nh + 5 * fx + 4 * fy
+
+
+def stage_bytes(stage, n1, n2, n3, r, mixed):
+    """Algorithmic bytes of one launch of each stage (what the kernel must read and write)."""
+    nb = n3 // 2 + 1
+    nh = n1 * n2 * nb
+    sw = 4 if mixed else 8
+    fx, fy = 8 * nb * r * n1, 8 * nb * r * n2
+    return {
+        "slice": 8 * nh + 4 * n1 * n2 * n3 + sw * nh,   # read Z~ and G, write W~
+        "zgemm": fx + fy + 8 * nh,                       # read X~, Y~, write Z~
+        "agemm": sw * nh + fy + fx + fx,                 # read W~, Y~, X~, write the X right-hand side
+        "hsolve": 2 * fx,                                # read the right-hand side, write X~
+        "bgemm": sw * nh + fx + fy,                      # read W~ and X~, write X~^* W~
+        "ystep": 2 * fy,                                 # read and write Y~
+    }[stage]
+
+
+def run_precision(prec, d, w, steps, warmup, dev, torch):
+    from paper_2005_09838_amd import Completion
+    t = lambda a: torch.from_numpy(a).to(dev)
+    c = Completion(t(d["G"]), t(d["omega"]), w.r, mu=w.mu, rho1=w.rho1, rho2=w.rho2, precision=prec,
+                   X0=t(d["X0"]), Y0=t(d["Y0"]))
+    c.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = {name: c.time_stage(name, 20) for name in ("slice", "zgemm", "agemm", "hsolve", "bgemm", "ystep")}
+    return c, dt, stages
+
+
+def rse_history(prec, d, w, iters, every, dev, torch, M):
+    from paper_2005_09838_amd import Completion
+    t = lambda a: torch.from_numpy(a).to(dev)
+    c = Completion(t(d["G"]), t(d["omega"]), w.r, mu=w.mu, rho1=w.rho1, rho2=w.rho2, precision=prec,
+                   X0=t(d["X0"]), Y0=t(d["Y0"]))
+    hist = []
+    done = 0
+    while done < iters:
+        k = min(every, iters - done)
+        c.step(k)
+        done += k
+        W = c.result()["W"]
+        hist.append((done, float(torch.linalg.norm(W - M) / torch.linalg.norm(M))))
+    c.close()
+    return hist
+
+
+def cpu_baseline(d, w, iters):
+    """The FP64 oracle on the host, single-threaded and with all cores, for `iters` iterations."""
+    import numpy as np  # noqa: F401
+    import oracle
+    from threadpoolctl import threadpool_limits
+
+    out = {}
+    for label, threads in (("one_core", 1), ("all_cores", min(16, os.cpu_count() or 1))):
+        with threadpool_limits(limits=threads):
+            prob = oracle.Problem(d["G"], d["omega"], w.r, w.mu, w.rho1, w.rho2)
+            st = oracle.initial_state(prob, d["X0"], d["Y0"])
+            t0 = time.perf_counter()
+            for _ in range(iters):
+                st = oracle.iterate(prob, st)
+            dt = time.perf_counter() - t0
+        out[label] = {"iters_per_s": iters / dt, "cores": threads, "seconds": dt, "state": st}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--rse-iters", type=int, default=200)
+    ap.add_argument("--oracle-iters", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build runs a completion on a single MI355X "
+              "(--gpus 1); multi-GPU runs are not part of it.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from synth import make_workload
+
+    w, d = make_workload(WORKLOAD)
+    dev = torch.device("cuda:0")
+    M = torch.from_numpy(d["M"]).to(dev)
+    n1, n2, n3, r = w.n1, w.n2, w.n3, w.r
+    res = {}
+    for prec in ("fp32", "mixed"):
+        c, dt, stages = run_precision(prec, d, w, args.steps, args.warmup, dev, torch)
+        mixed = prec == "mixed"
+        ips = args.steps / dt
+        W = c.result()["W"]
+        rse_end = float(torch.linalg.norm(W - M) / torch.linalg.norm(M))
+        dominant = max(stages, key=stages.get)
+        res[prec] = {
+            "iters_per_s": ips,
+            "ms_per_step": 1000.0 * dt / args.steps,
+            "hbm_gbps_algorithmic": algorithmic_bytes(n1, n2, n3, r, mixed) * ips / 1e9,
+            "stage_us": {k: round(v, 3) for k, v in stages.items()},
+            "dominant_kernel": dominant,
+            "stage_gbps": {k: round(stage_bytes(k, n1, n2, n3, r, mixed) / (v * 1e-6) / 1e9, 1)
+                           for k, v in stages.items()},
+            "rse_after_timed_run": rse_end,
+            "iterations_at_rse": args.warmup + args.steps,
+        }
+        c.close()
+
+    # equal-error protocol
+    every = 10
+    h32 = rse_history("fp32", d, w, args.rse_iters, every, dev, torch, M)
+    hmx = rse_history("mixed", d, w, args.rse_iters, every, dev, torch, M)
+    rse32 = h32[-1][1]
+    t_equal = next((it for it, v in hmx if v <= rse32 * (1 + 5e-3)), None)
+    res["fp32"]["rse"] = rse32
+    res["mixed"]["rse"] = hmx[-1][1]
+    res["mixed"]["rse_gap_rel"] = hmx[-1][1] / rse32 - 1.0
+    res["mixed"]["iters_to_fp32_rse"] = t_equal
+    res["fp32"]["rse_history"] = h32
+    res["mixed"]["rse_history"] = hmx
+    for prec in ("fp32", "mixed"):
+        it = args.rse_iters if prec == "fp32" else t_equal
+        res[prec]["seconds_to_fp32_rse"] = None if it is None else it / res[prec]["iters_per_s"]
+
+    # error against the FP64 oracle after the oracle's sample, and the CPU baseline
+    cpu = None
+    if not args.no_cpu and args.oracle_iters > 0:
+        base = cpu_baseline(d, w, args.oracle_iters)
+        st = base["one_core"]["state"]
+        for prec in ("fp32", "mixed"):
+            from paper_2005_09838_amd import Completion
+            t = lambda a: torch.from_numpy(a).to(dev)
+            c = Completion(t(d["G"]), t(d["omega"]), r, mu=w.mu, rho1=w.rho1, rho2=w.rho2, precision=prec,
+                           X0=t(d["X0"]), Y0=t(d["Y0"]))
+            c.step(args.oracle_iters)
+            Wg = c.result()["W"].cpu().numpy().astype(np.float64)
+            c.close()
+            res[prec][f"rel_err_vs_fp64_oracle_after_{args.oracle_iters}_iters"] = float(
+                np.linalg.norm(Wg - st.w) / np.linalg.norm(st.w))
+        cpu = {"value": base["one_core"]["iters_per_s"], "unit": "iters/s", "cores": 1, "kind": "oracle",
+               "sample": f"{args.oracle_iters} iterations of the FP64 NumPy oracle at {WORKLOAD} (single BLAS thread)",
+               "all_cores": {"value": base["all_cores"]["iters_per_s"], "cores": base["all_cores"]["cores"]}}
+
+    # headline: the faster precision among those that reach the FP32 error
+    head = "fp32"
+    if t_equal is not None and res["mixed"]["iters_per_s"] > res["fp32"]["iters_per_s"]:
+        head = "mixed"
+    hr = res[head]
+    dom = hr["dominant_kernel"]
+    dom_us = hr["stage_us"][dom]
+    achieved = stage_bytes(dom, n1, n2, n3, r, head == "mixed") / (dom_us * 1e-6) / 1e9
+    line = {
+        "metric": "completion iters/s + HBM GB/s at 529x96x112 r=16, mixed vs FP32 at equal RSE",
+        "value": round(hr["iters_per_s"], 2),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(hr["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "fp32" else "bf16-operands/f32-accumulate",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n1": n1, "n2": n2, "n3": n3, "r": r, "sampling": w.p,
+                   "mu": w.mu, "rho1": w.rho1, "rho2": w.rho2, "headline_precision": head},
+        "hbm_gbps": round(hr["hbm_gbps_algorithmic"], 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "kernel": f"{dom} ({head})", "kernel_us": round(dom_us, 3),
+                     "bytes_per_launch": stage_bytes(dom, n1, n2, n3, r, head == "mixed")},
+        "cpu_baseline": cpu,
+        "precisions": {k: {kk: vv for kk, vv in v.items() if kk != "rse_history"} for k, v in res.items()},
+        "rse_history": {"fp32": res["fp32"]["rse_history"], "mixed": res["mixed"]["rse_history"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -52,9 +52,10 @@ typedef enum {
 typedef enum {
   TCTF_FP32 = 0,        /* FP32 storage and products; the reduction over n1 of X~^* W~
                            accumulates in FP64; r x r Grams, pseudo-inverses, objective FP64 */
-  TCTF_MIXED_BF16 = 1   /* W~ stored in BF16; the three slice products take BF16 operands
-                           with FP32 accumulation; factors, G and W stay FP32; r x r Grams,
-                           pseudo-inverses and objective FP64                                */
+  TCTF_MIXED_BF16 = 1   /* W~ stored in BF16 (half the bytes of its write and reads); the
+                           slice products take the BF16 W~ and FP32 factors and accumulate
+                           in FP32; factors, G and W stay FP32; r x r Grams, pseudo-inverses
+                           and objective FP64                                                */
 } tctf_precision;
 
 typedef struct {
@@ -72,7 +73,8 @@ typedef struct {
   double eps;           /* threshold of the termination test (step 6), default 1e-6        */
 } tctf_params;
 /* Supported n3: 1..16, 20, 24, 28, 32, 40, 48, 56, 64, 84, 96, 112, 128 (the tube
- * transform is generated for these lengths).  n2 <= 1024, n1 <= 65536. */
+ * transform is generated for these lengths).  n1 <= 8192, n2 <= 1024, and one slice
+ * (n2 x (n3 + 1) floats) must fit the slice kernel's 150 KiB of LDS. */
 
 typedef struct tctf_ctx tctf_ctx;
 

@@ -312,6 +312,39 @@ def gen_inverse(n):
     return emit_function(sig, g, outs)
 
 
+# ---------------------------------------------------------------- LDS four-step plans
+
+def lds_factor(n):
+    """(M1, M2) with M1 * M2 = n/2 and both <= 16 for the LDS four-step transform, or None."""
+    if n % 2 or n < 16:
+        return None
+    m = n // 2
+    best = None
+    for m1 in range(2, 17):
+        if m % m1 == 0 and 2 <= m // m1 <= 16:
+            cand = (abs(m1 - m // m1), -m1, m1, m // m1)
+            best = cand if best is None or cand < best else best
+    return None if best is None else (best[2], best[3])
+
+
+def gen_small_complex(p, sigma):
+    """In-place complex DFT of length p: y[k] = sum_n x[n] exp(sigma 2 pi i n k / p)."""
+    g = Gen()
+    xs = [((1, f"re[{q}]"), (1, f"im[{q}]")) for q in range(p)]
+    ys = g.fft(xs, sigma)
+    outs = []
+    for k in range(p):
+        outs.append((f"o_re[{k}]", ys[k][0]))
+        outs.append((f"o_im[{k}]", ys[k][1]))
+    tag = "p" if sigma > 0 else "n"
+    sig = f"template <> TUBE_DFT_QUAL void dftc<{p}, {sigma}>(float (&re)[{p}], float (&im)[{p}])"
+    body, cnt = emit_function(sig, g, outs)
+    # write through temporaries so the outputs may alias the inputs
+    body = body.replace(sig + " {", sig + " {\n  float o_re[%d], o_im[%d];" % (p, p), 1)
+    body = body[:-1] + "  for (int k = 0; k < %d; ++k) { re[k] = o_re[k]; im[k] = o_im[k]; }\n}" % p
+    return body, cnt
+
+
 def main(path):
     parts = [
         "// Generated by gen_tube_dft.py: straight-line tube transforms (do not edit).",
@@ -326,6 +359,17 @@ def main(path):
         "template <int N> TUBE_DFT_QUAL void tube_inv(const float (&re)[N / 2 + 1], const float (&im)[N / 2 + 1], float (&x)[N]);",
         "#define TUBE_DFT_SIZES(X) " + " ".join(f"X({n})" for n in SIZES),
     ]
+    parts.append("template <int P, int S> TUBE_DFT_QUAL void dftc(float (&re)[P], float (&im)[P]);")
+    plans = {n: lds_factor(n) for n in SIZES}
+    smalls = sorted({f for pl in plans.values() if pl for f in pl})
+    for q in smalls:
+        for sg in (+1, -1):
+            parts.append(gen_small_complex(q, sg)[0])
+    parts.append("// Four-step plan of each tube length that runs through LDS: N/2 = M1 * M2 (0 = registers).")
+    parts.append("template <int N> struct TubePlan { static constexpr int M1 = 0, M2 = 0; };")
+    for n, pl in plans.items():
+        if pl:
+            parts.append(f"template <> struct TubePlan<{n}> {{ static constexpr int M1 = {pl[0]}, M2 = {pl[1]}; }};")
     stats = []
     for n in SIZES:
         f, cf = gen_forward(n)

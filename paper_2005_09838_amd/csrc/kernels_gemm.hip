@@ -5,8 +5,8 @@
 //   X~_b^* W~_b, X~_b^* X~_b, (H X~_b)^*(H X~_b) partial sums over row chunks (step 2)
 //                                                                      k_bgemm
 // FP32 mode: FP32 operands; the n1 reduction of X~^* W~ accumulates in FP64.
-// Mixed mode: W~ is read from BF16 storage and X~, Y~ operands are rounded to BF16;
-// products accumulate in FP32.  r x r Grams are always FP64.
+// Mixed mode: W~ is read from BF16 storage (the factors stay FP32) and the products
+// accumulate in FP32.  r x r Grams are always FP64.
 #include "kernels.h"
 
 namespace tctf {
@@ -14,10 +14,10 @@ namespace tctf {
 __device__ __forceinline__ float2 ld_wt(const void* wt, size_t idx, int mixed) {
   return mixed ? unpack_bf16x2(((const uint32_t*)wt)[idx]) : ((const float2*)wt)[idx];
 }
-__device__ __forceinline__ cf to_cf(float2 v, int mixed) {
+__device__ __forceinline__ cf to_cf(float2 v, int) {
   cf c;
-  c.re = mixed ? bf16_round(v.x) : v.x;
-  c.im = mixed ? bf16_round(v.y) : v.y;
+  c.re = v.x;
+  c.im = v.y;
   return c;
 }
 
@@ -57,110 +57,137 @@ void launch_zgemm(const Plan& p) {
 }
 
 // ---------------------------------------------------------------- A = W~ Y~^*, X right-hand side
-// Tile: 16 rows of one frequency; thread (il, jl) accumulates A(i, :) over columns
-// j = jl (mod 16), then the 16 lanes of a row combine their sums.
+// Block: 64 rows of one frequency.  W~ and Y~ are staged through LDS in chunks of 64
+// columns (coalesced loads, all issued before use); thread (il, q) = (tid / 4, tid % 4)
+// accumulates A(i, s) for s = q, q + 4, ... in FP32.  The epilogue forms, in FP64,
+//   R(i, :) = eta A(i, :) G_Y^+ + (H_rho1 U)(i, :),  U = X~ (I - eta P_Y)
+// (U only when I - eta P_Y is not exactly 0).
+#define AG_ROWS 64
+#define AG_COLS 64
 __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, const float2* __restrict__ yt,
                                                const float2* __restrict__ xt, const cd* __restrict__ gyp,
                                                const cd* __restrict__ qy, const int* __restrict__ qy_zero,
-                                               const float* __restrict__ htab, float2* __restrict__ rhs,
-                                               int n1, int n2, int r, int nb, double eta, double rho1, int mixed,
-                                               int raw_a) {
-  __shared__ cf ych[TCTF_RMAX][64];
+                                               float2* __restrict__ rhs, int n1, int n2, int r, int nb,
+                                               double eta, double rho1, int mixed, int raw_a) {
+  __shared__ float2 wsh[AG_ROWS][AG_COLS + 1];
+  __shared__ float2 ysh[TCTF_RMAX][AG_COLS + 1];
   __shared__ cd gs[TCTF_RMAX * TCTF_RMAX];
   __shared__ cd qs[TCTF_RMAX * TCTF_RMAX];
-  __shared__ cf xh[18][TCTF_RMAX];
-  const int i0 = blockIdx.x * 16, b = blockIdx.y, tid = threadIdx.x;
-  const int il = tid >> 4, jl = tid & 15, i = i0 + il;
-  float acc_re[TCTF_RMAX], acc_im[TCTF_RMAX];
+  const int i0 = blockIdx.x * AG_ROWS, b = blockIdx.y, tid = threadIdx.x;
+  const int il = tid >> 2, q = tid & 3, i = i0 + il;
+  constexpr int SP = TCTF_RMAX / 4;   // outputs per thread at most
+  float accr[SP], acci[SP];
 #pragma unroll
-  for (int s = 0; s < TCTF_RMAX; ++s) { acc_re[s] = 0.f; acc_im[s] = 0.f; }
-  for (int j0 = 0; j0 < n2; j0 += 64) {
+  for (int u = 0; u < SP; ++u) { accr[u] = 0.f; acci[u] = 0.f; }
+  for (int j0 = 0; j0 < n2; j0 += AG_COLS) {
+    const int nc = min(AG_COLS, n2 - j0);
     __syncthreads();
-    for (int e = tid; e < r * 64; e += 256) {
-      const int s = e >> 6, jj = e & 63, j = j0 + jj;
-      ych[s][jj] = (j < n2) ? to_cf(yt[((size_t)b * r + s) * n2 + j], mixed) : cf{0.f, 0.f};
+    {
+      float2 v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {   // 64 x 64 tile, 16 elements per thread
+        const int e = tid + 256 * u, rr = e >> 6, cc = e & 63;
+        const int ii = i0 + rr;
+        v[u] = (ii < n1 && cc < nc) ? ld_wt(wt, ((size_t)ii * nb + b) * n2 + j0 + cc, mixed) : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u;
+        wsh[e >> 6][e & 63] = v[u];
+      }
+    }
+    for (int e = tid; e < r * AG_COLS; e += 256) {
+      const int s = e >> 6, cc = e & 63;
+      ysh[s][cc] = cc < nc ? yt[((size_t)b * r + s) * n2 + j0 + cc] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    if (i < n1) {
-      for (int jj = jl; jj < 64 && j0 + jj < n2; jj += 16) {
-        const float2 w = ld_wt(wt, ((size_t)i * nb + b) * n2 + j0 + jj, mixed);
+#pragma unroll 4
+    for (int cc = 0; cc < AG_COLS; ++cc) {
+      const float2 w = wsh[il][cc];
 #pragma unroll
-        for (int s = 0; s < TCTF_RMAX; ++s) {
-          if (s < r) {
-            const cf y = ych[s][jj];   // w * conj(y)
-            acc_re[s] = fmaf(w.x, y.re, fmaf(w.y, y.im, acc_re[s]));
-            acc_im[s] = fmaf(w.y, y.re, fmaf(-w.x, y.im, acc_im[s]));
-          }
+      for (int u = 0; u < SP; ++u) {
+        const int s = q + 4 * u;
+        if (s < r) {
+          const float2 y = ysh[s][cc];   // w * conj(y)
+          accr[u] = fmaf(w.x, y.x, fmaf(w.y, y.y, accr[u]));
+          acci[u] = fmaf(w.y, y.x, fmaf(-w.x, y.y, acci[u]));
         }
       }
     }
   }
+  // epilogue: A rows through LDS (reusing the W~ tile)
+  __syncthreads();
+  float2* ash = &wsh[0][0];   // [AG_ROWS][r]
 #pragma unroll
-  for (int s = 0; s < TCTF_RMAX; ++s) {
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
-      acc_re[s] += __shfl_xor(acc_re[s], off);
-      acc_im[s] += __shfl_xor(acc_im[s], off);
+  for (int u = 0; u < SP; ++u) {
+    const int s = q + 4 * u;
+    if (s < r) ash[il * r + s] = make_float2(accr[u], acci[u]);
+  }
+  if (raw_a) {
+    __syncthreads();
+    for (int e = tid; e < AG_ROWS * r; e += 256) {
+      const int s = e / AG_ROWS, rr = e % AG_ROWS;
+      if (i0 + rr < n1) rhs[((size_t)b * r + s) * n1 + i0 + rr] = ash[rr * r + s];
     }
+    return;
   }
   const int noqy = qy_zero[b];
   for (int e = tid; e < r * r; e += 256) {
     gs[e] = gyp[(size_t)b * r * r + e];
     qs[e] = qy[(size_t)b * r * r + e];
   }
-  for (int e = tid; e < r * 18; e += 256) {
-    const int s = e / 18, hl = e % 18, ih = i0 - 1 + hl;
-    const float2 v = (ih >= 0 && ih < n1) ? xt[((size_t)b * r + s) * n1 + ih] : make_float2(0.f, 0.f);
-    xh[hl][s] = cf{v.x, v.y};
+  __syncthreads();
+  float2* res = ash + AG_ROWS * TCTF_RMAX;   // [AG_ROWS][r] results, transposed store below
+  if (i < n1) {
+    const double deg = (n1 == 1) ? 0.0 : ((i == 0 || i == n1 - 1) ? 1.0 : 2.0);
+    const double dii = 1.0 + rho1 * deg;
+    for (int s = q; s < r; s += 4) {
+      cd t = cd_make(0.0, 0.0);
+      for (int u = 0; u < r; ++u) {
+        const float2 av = ash[il * r + u];
+        cd_fma(t, cd_make(av.x, av.y), gs[u * r + s]);
+      }
+      t = cd_scale(t, eta);
+      if (!noqy) {
+        cd uu[3];
+        for (int h = 0; h < 3; ++h) {
+          uu[h] = cd_make(0.0, 0.0);
+          const int ih = i - 1 + h;
+          if (ih < 0 || ih >= n1) continue;
+          for (int v2 = 0; v2 < r; ++v2) {
+            const float2 xv = xt[((size_t)b * r + v2) * n1 + ih];
+            cd_fma(uu[h], cd_make(xv.x, xv.y), qs[v2 * r + s]);
+          }
+        }
+        // (H_rho1 U)_i = (1 + rho1 deg_i) U_i - rho1 (U_{i-1} + U_{i+1}); outside rows are 0
+        t = cd_add(t, cd_sub(cd_scale(uu[1], dii), cd_scale(cd_add(uu[0], uu[2]), rho1)));
+      }
+      res[il * r + s] = make_float2((float)t.re, (float)t.im);
+    }
   }
   __syncthreads();
-  if (i >= n1) return;
-  const double deg = (n1 == 1) ? 0.0 : ((i == 0 || i == n1 - 1) ? 1.0 : 2.0);
-  const double dii = 1.0 + rho1 * deg;
-  if (raw_a) {   // A itself (stationarity measures)
-    for (int s = jl; s < r; s += 16) {
-      float ar = 0.f, ai = 0.f;
-#pragma unroll
-      for (int q = 0; q < TCTF_RMAX; ++q)
-        if (q == s) { ar = acc_re[q]; ai = acc_im[q]; }
-      rhs[((size_t)b * r + s) * n1 + i] = make_float2(ar, ai);
-    }
-    return;
+  for (int e = tid; e < AG_ROWS * r; e += 256) {   // coalesced along i
+    const int s = e / AG_ROWS, rr = e % AG_ROWS;
+    if (i0 + rr < n1) rhs[((size_t)b * r + s) * n1 + i0 + rr] = res[rr * r + s];
   }
-  for (int s = jl; s < r; s += 16) {
-    cd t = cd_make(0.0, 0.0);
-#pragma unroll
-    for (int q = 0; q < TCTF_RMAX; ++q)
-      if (q < r) cd_fma(t, cd_make(acc_re[q], acc_im[q]), gs[q * r + s]);
-    t = cd_scale(t, eta);
-    if (!noqy) {
-      cd u[3];
-      for (int h = 0; h < 3; ++h) {
-        u[h] = cd_make(0.0, 0.0);
-        for (int q = 0; q < r; ++q) cd_fma(u[h], cd_make(xh[il + h][q].re, xh[il + h][q].im), qs[q * r + s]);
-      }
-      // (H_rho1 U)_i = (1 + rho1 deg_i) U_i - rho1 (U_{i-1} + U_{i+1}); outside rows are 0
-      t = cd_add(t, cd_sub(cd_scale(u[1], dii), cd_scale(cd_add(u[0], u[2]), rho1)));
-    }
-    rhs[((size_t)b * r + s) * n1 + i] = make_float2((float)t.re, (float)t.im);
-  }
-  (void)htab;
 }
 
 void launch_agemm(const Plan& p, int raw_a) {
-  dim3 grid((p.n1 + 15) / 16, p.nb);
-  k_agemm<<<grid, 256, 0, p.stream>>>(p.wt, p.yt, p.xt, p.gyp, p.qy, p.qy_zero, p.htab, p.rhs, p.n1, p.n2,
-                                      p.r, p.nb, p.eta, p.rho1, p.mixed, raw_a);
+  dim3 grid((p.n1 + AG_ROWS - 1) / AG_ROWS, p.nb);
+  k_agemm<<<grid, 256, 0, p.stream>>>(p.wt, p.yt, p.xt, p.gyp, p.qy, p.qy_zero, p.rhs, p.n1, p.n2, p.r, p.nb,
+                                      p.eta, p.rho1, p.mixed, raw_a);
 }
 
 // ---------------------------------------------------------------- X~^* W~ and Gram partials
-// Block (j-tile, chunk c, frequency b): rows [c*chunk, min(n1, (c+1)*chunk)).
+// Block (j-tile of 64, chunk c, frequency b): rows [c*chunk, min(n1, (c+1)*chunk)).  The
+// X~ rows of the chunk sit in LDS; W~ is staged 16 rows at a time (coalesced loads).
 template <typename Acc>
 __global__ void __launch_bounds__(256) k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt,
                                                float2* __restrict__ bpart, cd* __restrict__ spart,
                                                cd* __restrict__ dpart, int n1, int n2, int r, int nb,
                                                int nchunk, int chunk, int mixed) {
   extern __shared__ cf xc[];   // [chunk + 1][r]
+  __shared__ float2 wsh[16][64];
   const int j0 = blockIdx.x * 64, c = blockIdx.y, b = blockIdx.z, tid = threadIdx.x;
   const int i0 = c * chunk, i1 = min(n1, i0 + chunk);
   const int rows = i1 - i0 + ((i1 < n1) ? 1 : 0);
@@ -169,28 +196,45 @@ __global__ void __launch_bounds__(256) k_bgemm(const void* __restrict__ wt, cons
     const float2 v = xt[((size_t)b * r + s) * n1 + i0 + h];
     xc[h * r + s] = cf{v.x, v.y};
   }
-  __syncthreads();
   const int jl = tid & 63, sg = tid >> 6, j = j0 + jl;
   constexpr int U = TCTF_RMAX / 4;
   Acc are[U], aim[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) { are[u] = 0; aim[u] = 0; }
-  if (j < n2) {
-    for (int i = i0; i < i1; ++i) {
-      const float2 w = ld_wt(wt, ((size_t)i * nb + b) * n2 + j, mixed);
+  for (int ib = i0; ib < i1; ib += 16) {
+    const int nr = min(16, i1 - ib);
+    __syncthreads();
+    {
+      float2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {   // 16 x 64 tile, 4 elements per thread
+        const int e = tid + 256 * u, rr = e >> 6, cc = e & 63;
+        v[u] = (rr < nr && j0 + cc < n2) ? ld_wt(wt, ((size_t)(ib + rr) * nb + b) * n2 + j0 + cc, mixed)
+                                         : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = tid + 256 * u;
+        wsh[e >> 6][e & 63] = v[u];
+      }
+    }
+    __syncthreads();
+    for (int rr = 0; rr < nr; ++rr) {
+      const float2 w = wsh[rr][jl];
       const Acc wr = w.x, wi = w.y;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int s = sg + 4 * u;
         if (s < r) {
-          cf x = xc[(i - i0) * r + s];
-          if (mixed) { x.re = bf16_round(x.re); x.im = bf16_round(x.im); }
+          const cf x = xc[(ib + rr - i0) * r + s];
           const Acc xr = x.re, xi = x.im;   // conj(x) * w
           are[u] = fma(xr, wr, fma(xi, wi, are[u]));
           aim[u] = fma(xr, wi, fma(-xi, wr, aim[u]));
         }
       }
     }
+  }
+  if (j < n2) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int s = sg + 4 * u;

@@ -13,12 +13,16 @@
 //   (1 + mu + rho2 deg_j) w_j - rho2 (w_{j-1} + w_{j+1}) = z_j,
 // a tridiagonal system with the observed neighbours on the right-hand side.  Thomas
 // elimination needs no pivoting (strict diagonal dominance); its reciprocal pivots depend
-// only on the run position, so they come from the precomputed table, and each pass is one
-// dependent multiply-add per entry:
+// only on the position in the run of unobserved entries (and on whether the run starts
+// at the first slot), so they come from the precomputed table.  The row's observed flags
+// sit in an LDS bitmask; the forward pass counts the run position, the backward pass
+// recovers each run's start from the flags.  Each pass is one dependent multiply-add per
+// entry, entirely in LDS:
 //   forward  y_j = (z_j + rho2 y_{j-1}) / alpha_j      (y = g on observed entries)
 //   backward w_j = y_j + rho2 / alpha_j * w_{j+1}       (w = g on observed entries)
 #include "kernels.h"
 #include "tube_dft_gen.h"
+#include "tube_lds.h"
 
 namespace tctf {
 
@@ -54,92 +58,154 @@ __device__ __forceinline__ void load_inverse_tube(const float2* __restrict__ zt,
   tube_inv<N>(re, im, z);
 }
 
+// LDS row stride of one tube: odd (bank-conflict-free across tubes) and, for the LDS
+// transforms, at least N floats of workspace.
 template <int N>
+__host__ __device__ constexpr int slice_ld() { return (N % 2 == 0) ? N + 3 : N + 2; }
+
+template <int N, int MODE>
 __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
   constexpr int NB = N / 2 + 1;
-  constexpr int LD = N + 1;
+  constexpr int LD = slice_ld<N>();
+  constexpr bool LDSFFT = TubeLds<N>::enabled;
+  constexpr int M = N / 2;
   extern __shared__ float smem[];
-  const int n2 = a.n2;
-  float* zs = smem;                         // [n2][N+1]
-  float* tab = smem + (size_t)n2 * LD;      // [4][n2]
-  const size_t red_off = (size_t)n2 * LD + 4 * (size_t)n2;
-  double* red = (double*)(smem + red_off + (red_off & 1));
+  const int n2 = a.n2, nwr = (n2 + 31) >> 5;
+  float* zs = smem;                                   // [n2][LD]
+  float* tab = zs + (size_t)n2 * LD;                  // [4][n2]
+  uint32_t* obits = (uint32_t*)(tab + 4 * n2);        // [N][nwr]: bit j of row k = (i, j, k) observed
+  int* cstate = (int*)(obits + N * nwr);              // [N][nwr]: run position and "seen" at each 32-column chunk
+  size_t off = (size_t)n2 * LD + 4 * (size_t)n2 + 2 * (size_t)N * nwr;
+  off += off & 1;
+  float2* twm = (float2*)(smem + off);                // [M]   (LDS transforms only)
+  float2* twn = twm + (LDSFFT ? M : 0);               // [M+1]
+  double* red = (double*)(twn + (LDSFFT ? M + 1 : 0));
   const size_t i = blockIdx.x;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const bool thomas = !(a.mode == SLICE_INIT || a.w_from_g);
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  const bool thomas = MODE != SLICE_INIT && !a.w_from_g;
   const float* gslice = a.gp + i * n2 * N;
 
+  // ---- 0. tables
   for (int e = tid; e < 4 * n2; e += nt) tab[e] = a.wtab[e];
+  if constexpr (LDSFFT) tube_twiddles<N>(twm, twn);
+  __syncthreads();
 
-  // ---- 1. inverse transform of Z~(i, j, :) (skipped when W is P_Omega(G) only)
-  const bool need_z = !(a.mode == SLICE_RESULT && a.w_from_g && a.z_out == nullptr);
+  // ---- 1. inverse transform of Z~(i, j, :); observed entries take G, the others Z; the
+  //         fit term of observed entries (of all entries when W = P_Omega(G)) is taken here
+  //         and the observed flags of each row (i, :, k) become a bitmask over j (wave
+  //         ballots: the tube loop keeps each wave on 64 consecutive tubes).
+  double fit = 0.0, ridge = 0.0, sm = 0.0;
+  const bool need_z = !(MODE == SLICE_RESULT && a.w_from_g && a.z_out == nullptr);
   for (int j = tid; j < n2; j += nt) {
+    float* row = zs + j * LD;
     float z[N];
     if (need_z) {
-      load_inverse_tube<N>(a.zt, i, j, a.nb, n2, z);
+      if constexpr (LDSFFT) {
+        tube_inv_lds<N>(a.zt + i * a.nb * n2 + j, n2, row, twm, twn);
+        constexpr float inv_m = 1.0f / M;
+#pragma unroll
+        for (int q = 0; q < N; ++q) z[q] = row[TubeLds<N>::xpos(q)] * inv_m;
+      } else {
+        load_inverse_tube<N>(a.zt, i, j, a.nb, n2, z);
+      }
     } else {
 #pragma unroll
       for (int q = 0; q < N; ++q) z[q] = 0.0f;
     }
-#pragma unroll
-    for (int q = 0; q < N; ++q) zs[j * LD + q] = z[q];
     if (a.z_out) {
       float* dst = a.z_out + (i * n2 + j) * N;
 #pragma unroll
       for (int q = 0; q < N; ++q) dst[q] = z[q];
     }
+    const float* g = gslice + (size_t)j * N;
+    const int jw0 = (j - lane) >> 5;   // first flag word of this wave's tubes
+    float facc = 0.0f;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const float gv = g[q];
+      const bool obs = !is_unobserved(gv);
+      float wv, d;
+      if (!thomas) {
+        wv = obs ? gv : 0.0f;
+        d = z[q] - wv;
+      } else {
+        wv = obs ? gv : z[q];
+        d = obs ? z[q] - gv : 0.0f;
+      }
+      facc = fmaf(d, d, facc);
+      row[q] = wv;
+      // the wave's 64 consecutive tubes give two words of row q's flags
+      const uint64_t bal = __ballot(obs);
+      if (lane < 2 && jw0 + lane < nwr) obits[q * nwr + jw0 + lane] = (uint32_t)(bal >> (32 * lane));
+    }
+    fit += (double)facc;
   }
   __syncthreads();
 
-  // ---- 2. W-step along mode 2 for the rows (i, :, k); the fit term of observed entries
-  //         (and, for W = P_Omega(G), of all entries) is taken while Z is still in LDS
-  double fit = 0.0, ridge = 0.0, sm = 0.0;
-  for (int k = tid; k < N; k += nt) {
-    const float* g = gslice + k;
-    if (!thomas) {
-      for (int jj = 0; jj < n2; ++jj) {
-        const float gv = g[(size_t)jj * N];
-        const float zv = zs[jj * LD + k];
-        const float wv = is_unobserved(gv) ? 0.0f : gv;
-        const double d = (double)zv - (double)wv;
-        fit += d * d;
-        zs[jj * LD + k] = wv;
-      }
-    } else {
-      const float rho2 = a.rho2;
+  // ---- 2. W-step along mode 2 for the rows (i, :, k), 32 columns at a time: the values
+  //         and pivots of a chunk are read from LDS together, then the recurrence runs in
+  //         registers.  The run position at each chunk start is kept for the backward pass.
+  if (thomas) {
+    const float rho2 = a.rho2;
+    for (int k = tid; k < N; k += nt) {
+      const uint32_t* ob = obits + k * nwr;
+      int* cs = cstate + k * nwr;
       float y = 0.0f;
-      for (int jj = 0; jj < n2; ++jj) {
-        const float gv = g[(size_t)jj * N];
-        const float zv = zs[jj * LD + k];
-        if (is_unobserved(gv)) {
-          const int sel = (jj == n2 - 1 ? 2 : 0) + (unobs_starts_row(gv) ? 0 : 1);
-          const float inv = tab[sel * n2 + unobs_pos(gv)];
-          y = fmaf(rho2, y, zv) * inv;
-        } else {
-          const double d = (double)zv - (double)gv;
-          fit += d * d;
-          y = gv;
+      int pos = 0, seen = 0;
+      for (int c = 0; c < nwr; ++c) {
+        const int j0 = c * 32, cnt = min(32, n2 - j0);
+        const uint32_t word = ob[c];
+        cs[c] = pos | (seen << 20);
+        float v[32], inv[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) v[u] = zs[min(j0 + u, n2 - 1) * LD + k];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+          const int o = (word >> u) & 1u;
+          const int sel = (j0 + u == n2 - 1 ? 2 : 0) + seen;
+          inv[u] = tab[o ? 0 : sel * n2 + min(pos, n2 - 1)];
+          seen |= o;
+          pos = o ? 0 : pos + 1;
         }
-        zs[jj * LD + k] = y;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+          const int o = (word >> u) & 1u;
+          y = o ? v[u] : fmaf(rho2, y, v[u]) * inv[u];
+          if (u < cnt) zs[(j0 + u) * LD + k] = y;
+        }
       }
       float w = 0.0f;
-      for (int jj = n2 - 1; jj >= 0; --jj) {
-        const float gv = g[(size_t)jj * N];
-        const float yv = zs[jj * LD + k];
-        if (is_unobserved(gv) && jj < n2 - 1) {
-          const int sel = unobs_starts_row(gv) ? 0 : 1;
-          const float inv = tab[sel * n2 + unobs_pos(gv)];
-          w = fmaf(rho2 * inv, w, yv);
-        } else {
-          w = yv;
+      for (int c = nwr - 1; c >= 0; --c) {
+        const int j0 = c * 32, cnt = min(32, n2 - j0);
+        const uint32_t word = ob[c];
+        const int st = cs[c];
+        int p = st & 0xfffff, sn = st >> 20;
+        float v[32], cf[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) v[u] = zs[min(j0 + u, n2 - 1) * LD + k];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+          const int o = (word >> u) & 1u;
+          // interior pivot; observed entries and the last column take no right neighbour
+          const float inv = tab[o ? 0 : sn * n2 + min(p, n2 - 1)];
+          cf[u] = (o || j0 + u >= n2 - 1) ? 0.0f : rho2 * inv;
+          sn |= o;
+          p = o ? 0 : p + 1;
         }
-        zs[jj * LD + k] = w;
+#pragma unroll
+        for (int u = 31; u >= 0; --u) {
+          if (u < cnt) {
+            w = fmaf(cf[u], w, v[u]);
+            zs[(j0 + u) * LD + k] = w;
+          }
+        }
       }
     }
   }
   __syncthreads();
 
-  // ---- 3. remaining objective terms and forward transform of W(i, j, :)
+  if (MODE == SLICE_KKT) fit = ridge = sm = 0.0;   // phase 3 takes maxima instead of sums
+  // ---- 3. remaining objective terms, then the forward transform of W(i, j, :).
   // For an unobserved entry the W-step equation gives
   //   z_j - w_j = (mu + rho2 deg_j) w_j - rho2 (w_{j-1} + w_{j+1}),
   // so the fit term there is formed from W alone.
@@ -147,59 +213,83 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
     const float* wrow = zs + j * LD;
     const bool has_l = j > 0, has_r = j + 1 < n2;
     const double cj = a.mu + a.rho2d * ((has_l ? 1.0 : 0.0) + (has_r ? 1.0 : 0.0));
-    const float* g = gslice + (size_t)j * N;
-    if (a.mode == SLICE_KKT) {
+    const int jw = j >> 5;
+    const uint32_t jb = 1u << (j & 31);
+    if constexpr (MODE == SLICE_KKT) {
       // residuals of eq. (subquKKT): unobserved (W K_{mu rho2} - Z)_ij, observed W - G
+      const float* g = gslice + (size_t)j * N;
       float z[N];
       load_inverse_tube<N>(a.zt, i, j, a.nb, n2, z);
 #pragma unroll
       for (int q = 0; q < N; ++q) {
-        const float gv = g[q];
+        const bool obs = obits[q * nwr + jw] & jb;
         const double wq = wrow[q];
-        if (is_unobserved(gv) && thomas) {
+        if (!obs && thomas) {
           const double l = has_l ? (double)wrow[q - LD] : 0.0;
           const double r = has_r ? (double)wrow[q + LD] : 0.0;
           fit = fmax(fit, fabs((1.0 + cj) * wq - a.rho2d * (l + r) - (double)z[q]));
-        } else if (!is_unobserved(gv)) {
-          ridge = fmax(ridge, fabs(wq - (double)gv));
+        } else if (obs) {
+          ridge = fmax(ridge, fabs(wq - (double)g[q]));
         }
         sm = fmax(sm, fabs((double)z[q]));
       }
-      continue;
-    }
-    for (int q = 0; q < N; ++q) {
-      const double wq = wrow[q];
-      ridge += wq * wq;
-      const double r = has_r ? (double)wrow[q + LD] : 0.0;
-      if (has_r) sm += (r - wq) * (r - wq);
-      if (thomas && is_unobserved(g[q])) {
-        const double l = has_l ? (double)wrow[q - LD] : 0.0;
-        const double d = cj * wq - a.rho2d * (l + r);
-        fit += d * d;
-      }
-    }
-    if (a.mode == SLICE_RESULT) {
-      if (a.w_out) {
-        float* dst = a.w_out + (i * n2 + j) * N;
-        for (int q = 0; q < N; ++q) dst[q] = wrow[q];
-      }
     } else {
-      float w[N], re[NB], im[NB];
-#pragma unroll
-      for (int q = 0; q < N; ++q) w[q] = wrow[q];
-      tube_fwd<N>(w, re, im);
-      if (a.mixed) {
-        uint32_t* dst = (uint32_t*)a.wt + i * a.nb * n2 + j;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) dst[(size_t)b * n2] = pack_bf16x2(re[b], im[b]);
-      } else {
-        float2* dst = (float2*)a.wt + i * a.nb * n2 + j;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) dst[(size_t)b * n2] = make_float2(re[b], im[b]);
+      const float cjf = (float)cj, r2f = a.rho2;
+      float fr = 0.0f, fs = 0.0f, ff = 0.0f;
+#pragma unroll 8
+      for (int q = 0; q < N; ++q) {
+        const float wq = wrow[q];
+        const float r = has_r ? wrow[q + LD] : 0.0f;
+        const float l = has_l ? wrow[q - LD] : 0.0f;
+        const bool un = thomas && !(obits[q * nwr + jw] & jb);
+        const float d = un ? fmaf(cjf, wq, -r2f * (l + r)) : 0.0f;
+        const float dr = has_r ? r - wq : 0.0f;
+        fr = fmaf(wq, wq, fr);
+        fs = fmaf(dr, dr, fs);
+        ff = fmaf(d, d, ff);
+      }
+      ridge += (double)fr;
+      sm += (double)fs;
+      fit += (double)ff;
+      if constexpr (MODE == SLICE_RESULT) {
+        if (a.w_out) {
+          float* dst = a.w_out + (i * n2 + j) * N;
+          for (int q = 0; q < N; ++q) dst[q] = wrow[q];
+        }
       }
     }
   }
-  if (a.mode == SLICE_KKT) {
+  if constexpr (MODE == SLICE_INIT || MODE == SLICE_ITER) {
+    if constexpr (LDSFFT) __syncthreads();   // the transforms below overwrite the rows
+    for (int j = tid; j < n2; j += nt) {
+      float* row = zs + j * LD;
+      const size_t base = i * a.nb * n2 + j;
+      if constexpr (LDSFFT) {
+        if (a.mixed) {
+          uint32_t* dst = (uint32_t*)a.wt + base;
+          tube_fwd_lds<N>(row, twm, twn, [&](int b, float re, float im) { dst[(size_t)b * n2] = pack_bf16x2(re, im); });
+        } else {
+          float2* dst = (float2*)a.wt + base;
+          tube_fwd_lds<N>(row, twm, twn, [&](int b, float re, float im) { dst[(size_t)b * n2] = make_float2(re, im); });
+        }
+      } else {
+        float w[N], re[NB], im[NB];
+#pragma unroll
+        for (int q = 0; q < N; ++q) w[q] = row[q];
+        tube_fwd<N>(w, re, im);
+        if (a.mixed) {
+          uint32_t* dst = (uint32_t*)a.wt + base;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) dst[(size_t)b * n2] = pack_bf16x2(re[b], im[b]);
+        } else {
+          float2* dst = (float2*)a.wt + base;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) dst[(size_t)b * n2] = make_float2(re[b], im[b]);
+        }
+      }
+    }
+  }
+  if constexpr (MODE == SLICE_KKT) {
     fit = block_max_d(fit, red);
     ridge = block_max_d(ridge, red);
     sm = block_max_d(sm, red);
@@ -208,7 +298,271 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
       a.kkt[3 * i + 1] = ridge;
       a.kkt[3 * i + 2] = sm;
     }
-  } else if (a.mode != SLICE_RESULT) {
+  } else if constexpr (MODE != SLICE_RESULT) {
+    fit = block_sum_d(fit, red);
+    ridge = block_sum_d(ridge, red);
+    sm = block_sum_d(sm, red);
+    if (tid == 0) {
+      a.slice_obj[3 * i + 0] = fit;
+      a.slice_obj[3 * i + 1] = ridge;
+      a.slice_obj[3 * i + 2] = sm;
+    }
+  }
+}
+
+
+
+// W-step of every row (i, :, k) with S threads per row: thread (k, s) takes columns
+// [s L, (s+1) L).  Both Thomas passes are first-order affine recurrences,
+//   forward  y_j = a_j y_{j-1} + b_j  (a = rho2 / alpha_j, b = v_j / alpha_j; a = 0, b = g_j observed)
+//   backward w_j = c_j w_{j+1} + y_j  (c = rho2 / alpha_j; c = 0 observed or at the last column),
+// so each thread composes its segment's map, the S maps of a row are combined by a
+// scan across the S lanes, and each thread then runs its segment once more from the
+// right boundary value.  S divides 64 and is a power of two; L <= LMAX.
+template <int LMAX>
+__device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* tab, const uint32_t* obits, int nwr,
+                                                int n2, int N, float rho2, int S) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int L = (n2 + S - 1) / S;
+  for (int kk = tid; kk < N * S; kk += nt) {
+    const int k = kk / S, s = kk - k * S;
+    const int ja = min(n2, s * L), jb = min(n2, ja + L);
+    const uint32_t* ob = obits + k * nwr;
+    // run state at ja: position in the current run of unobserved entries, and whether
+    // an observed entry precedes it
+    int seen, pos;
+    {
+      int w = ja >> 5;
+      uint32_t m = ja > 0 ? (ob[w] & ((1u << (ja & 31)) - 1u)) : 0u;
+      while (m == 0u && w > 0) m = ob[--w];
+      const int last = (m == 0u) ? -1 : (w * 32 + 31 - __clz(m));
+      seen = last >= 0;
+      pos = ja - last - 1;
+    }
+    float av[LMAX], bv[LMAX], cv[LMAX];
+    float A = 1.0f, B = 0.0f;
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u) {
+      const int j = ja + u;
+      if (j < jb) {
+        const bool o = (ob[j >> 5] >> (j & 31)) & 1u;
+        const float v = zs[j * LD + k];
+        const float invf = tab[o ? 0 : ((j == n2 - 1 ? 2 : 0) + seen) * n2 + pos];
+        const float invb = tab[o ? 0 : seen * n2 + pos];
+        av[u] = o ? 0.0f : rho2 * invf;
+        bv[u] = o ? v : v * invf;
+        cv[u] = (o || j == n2 - 1) ? 0.0f : rho2 * invb;
+        seen |= o;
+        pos = o ? 0 : pos + 1;
+        B = fmaf(av[u], B, bv[u]);
+        A *= av[u];
+      }
+    }
+    // forward: combine the segment maps of the row (lanes k*S .. k*S+S-1)
+    for (int d = 1; d < S; d <<= 1) {
+      const float a2 = __shfl_up(A, d, S), b2 = __shfl_up(B, d, S);
+      if (s >= d) { B = fmaf(A, b2, B); A *= a2; }
+    }
+    float y = __shfl_up(B, 1, S);
+    if (s == 0) y = 0.0f;
+    float C = 1.0f, D = 0.0f;
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u) {
+      if (ja + u < jb) {
+        y = fmaf(av[u], y, bv[u]);
+        bv[u] = y;   // y_j
+      }
+    }
+#pragma unroll
+    for (int u = LMAX - 1; u >= 0; --u) {
+      if (ja + u < jb) {
+        D = fmaf(cv[u], D, bv[u]);
+        C *= cv[u];
+      }
+    }
+    for (int d = 1; d < S; d <<= 1) {
+      const float c2 = __shfl_down(C, d, S), d2 = __shfl_down(D, d, S);
+      if (s + d < S) { D = fmaf(C, d2, D); C *= c2; }
+    }
+    float w = __shfl_down(D, 1, S);
+    if (s == S - 1) w = 0.0f;
+#pragma unroll
+    for (int u = LMAX - 1; u >= 0; --u) {
+      const int j = ja + u;
+      if (j < jb) {
+        w = fmaf(cv[u], w, bv[u]);
+        zs[j * LD + k] = w;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- cooperative slice kernel
+// The same three steps with T = M1 threads per tube (thread (t, j) = t * n2p + j, n2p = n2
+// rounded up to 64 so that every wave holds 64 consecutive tubes of one t).  The tube
+// transforms run through the tube's LDS row stage by stage; the W-step keeps one thread
+// per row.  Used when the block (T * n2p threads) fits 1024 threads.
+template <int N, int MODE>
+__global__ void __launch_bounds__(1024) k_slice_coop(SliceArgs a) {
+  using TL = TubeLds<N>;
+  constexpr int T = TL::M1, M1 = TL::M1, M2 = TL::M2, M = N / 2;
+  constexpr int LD = slice_ld<N>();
+  extern __shared__ float smem[];
+  const int n2 = a.n2, nwr = (n2 + 31) >> 5, n2p = (n2 + 63) & ~63;
+  float* zs = smem;                                   // [n2][LD]
+  float* tab = zs + (size_t)n2 * LD;                  // [4][n2]
+  uint32_t* obits = (uint32_t*)(tab + 4 * n2);        // [N][nwr]
+  int* cstate = (int*)(obits + N * nwr);              // [N][nwr]
+  size_t off = (size_t)n2 * LD + 4 * (size_t)n2 + 2 * (size_t)N * nwr;
+  off += off & 1;
+  float2* twm = (float2*)(smem + off);                // [M]
+  float2* twn = twm + M;                              // [M+1]
+  double* red = (double*)(twn + M + 1);
+  const size_t i = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  const int t = tid / n2p, j = tid - t * n2p;
+  const bool act = j < n2;
+  const bool thomas = MODE != SLICE_INIT && !a.w_from_g;
+  float* row = zs + (size_t)(act ? j : 0) * LD;
+  const float* gtube = a.gp + (i * n2 + (act ? j : 0)) * N;
+
+  for (int e = tid; e < 4 * n2; e += nt) tab[e] = a.wtab[e];
+  tube_twiddles<N>(twm, twn);
+  __syncthreads();
+
+  // ---- 1. inverse transform of Z~(i, j, :) (natural order in the row)
+  const bool need_z = !(MODE == SLICE_RESULT && a.w_from_g && a.z_out == nullptr);
+  if (need_z) {
+    if (act) tube_inv_pre<N>(a.zt + i * a.nb * n2 + j, n2, row, twn, t, T);
+    __syncthreads();
+    if (act) fft4_step_a<M1, M2, -1>(row, twm, t, T);
+    __syncthreads();
+    Fft4C<M1, M2> sc;
+    if (act) sc.read(row, t);
+    __syncthreads();
+    if (act) sc.template write<-1>(row, t);
+    __syncthreads();
+  }
+  // observed entries take G, the others Z; fit term of observed entries (all entries when
+  // W = P_Omega(G)); observed flags of each row (i, :, k) by wave ballots
+  double fit = 0.0, ridge = 0.0, sm = 0.0;
+  {
+    constexpr float inv_m = 1.0f / M;
+    const int jw0 = (j - lane) >> 5;
+    float facc = 0.0f;
+    for (int q = t; q < N; q += T) {
+      float zq = 0.0f, gv = 0.0f;
+      if (act) {
+        zq = need_z ? row[q] * inv_m : 0.0f;
+        gv = gtube[q];
+      }
+      const bool obs = act && !is_unobserved(gv);
+      float wv, d;
+      if (!thomas) {
+        wv = obs ? gv : 0.0f;
+        d = zq - wv;
+      } else {
+        wv = obs ? gv : zq;
+        d = obs ? zq - gv : 0.0f;
+      }
+      if (act) {
+        facc = fmaf(d, d, facc);
+        row[q] = wv;
+        if (a.z_out) a.z_out[(i * n2 + j) * N + q] = zq;
+      }
+      const uint64_t bal = __ballot(obs);
+      if (lane < 2 && jw0 + lane < nwr) obits[q * nwr + jw0 + lane] = (uint32_t)(bal >> (32 * lane));
+    }
+    fit += (double)facc;
+  }
+  __syncthreads();
+
+  // ---- 2. W-step along mode 2 for the rows (i, :, k), S threads per row
+  if (thomas) {
+    int S = 1;
+    while (S < 64 && 2 * S * N <= nt) S <<= 1;
+    while ((n2 + S - 1) / S > 16) S <<= 1;   // segment length within the register budget
+    wstep_segmented<16>(zs, LD, tab, obits, nwr, n2, N, a.rho2, S);
+  }
+  __syncthreads();
+
+  if (MODE == SLICE_KKT) fit = ridge = sm = 0.0;   // phase 3 takes maxima instead of sums
+  // ---- 3. remaining objective terms (see k_slice), then the forward transform
+  if (act) {
+    const bool has_l = j > 0, has_r = j + 1 < n2;
+    const int jw = j >> 5;
+    const uint32_t jb = 1u << (j & 31);
+    const double cj = a.mu + a.rho2d * ((has_l ? 1.0 : 0.0) + (has_r ? 1.0 : 0.0));
+    if constexpr (MODE == SLICE_KKT) {
+      if (t == 0) {
+        float z[N];
+        load_inverse_tube<N>(a.zt, i, j, a.nb, n2, z);
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          const bool obs = obits[q * nwr + jw] & jb;
+          const double wq = row[q];
+          if (!obs && thomas) {
+            const double l = has_l ? (double)row[q - LD] : 0.0;
+            const double r = has_r ? (double)row[q + LD] : 0.0;
+            fit = fmax(fit, fabs((1.0 + cj) * wq - a.rho2d * (l + r) - (double)z[q]));
+          } else if (obs) {
+            ridge = fmax(ridge, fabs(wq - (double)gtube[q]));
+          }
+          sm = fmax(sm, fabs((double)z[q]));
+        }
+      }
+    } else {
+      const float cjf = (float)cj, r2f = a.rho2;
+      float fr = 0.0f, fs = 0.0f, ff = 0.0f;
+      for (int q = t; q < N; q += T) {
+        const float wq = row[q];
+        const float r = has_r ? row[q + LD] : 0.0f;
+        const float l = has_l ? row[q - LD] : 0.0f;
+        const bool un = thomas && !(obits[q * nwr + jw] & jb);
+        const float d = un ? fmaf(cjf, wq, -r2f * (l + r)) : 0.0f;
+        const float dr = has_r ? r - wq : 0.0f;
+        fr = fmaf(wq, wq, fr);
+        fs = fmaf(dr, dr, fs);
+        ff = fmaf(d, d, ff);
+        if constexpr (MODE == SLICE_RESULT) {
+          if (a.w_out) a.w_out[(i * n2 + j) * N + q] = wq;
+        }
+      }
+      ridge += (double)fr;
+      sm += (double)fs;
+      fit += (double)ff;
+    }
+  }
+  if constexpr (MODE == SLICE_INIT || MODE == SLICE_ITER) {
+    __syncthreads();   // the transform below overwrites the rows
+    if (act) fft4_step_a<M1, M2, +1>(row, twm, t, T);
+    __syncthreads();
+    Fft4C<M1, M2> sc;
+    if (act) sc.read(row, t);
+    __syncthreads();
+    if (act) sc.template write<+1>(row, t);
+    __syncthreads();
+    if (act) {
+      const size_t base = i * a.nb * n2 + j;
+      if (a.mixed) {
+        uint32_t* dst = (uint32_t*)a.wt + base;
+        tube_fwd_post_nat<N>(row, twn, t, T, [&](int b, float re, float im) { dst[(size_t)b * n2] = pack_bf16x2(re, im); });
+      } else {
+        float2* dst = (float2*)a.wt + base;
+        tube_fwd_post_nat<N>(row, twn, t, T, [&](int b, float re, float im) { dst[(size_t)b * n2] = make_float2(re, im); });
+      }
+    }
+  }
+  if constexpr (MODE == SLICE_KKT) {
+    fit = block_max_d(fit, red);
+    ridge = block_max_d(ridge, red);
+    sm = block_max_d(sm, red);
+    if (tid == 0) {
+      a.kkt[3 * i + 0] = fit;
+      a.kkt[3 * i + 1] = ridge;
+      a.kkt[3 * i + 2] = sm;
+    }
+  } else if constexpr (MODE != SLICE_RESULT) {
     fit = block_sum_d(fit, red);
     ridge = block_sum_d(ridge, red);
     sm = block_sum_d(sm, red);
@@ -230,15 +584,40 @@ bool slice_supported(int n3) {
 }
 
 size_t slice_lds_bytes(int n2, int n3) {
-  return ((size_t)n2 * (n3 + 1) + 4 * (size_t)n2 + 2) * sizeof(float) + 16 * sizeof(double);
+  const size_t nwr = ((size_t)n2 + 31) / 32;
+  const size_t ld = (n3 % 2 == 0) ? n3 + 3 : n3 + 2;
+  size_t floats = (size_t)n2 * ld + 4 * (size_t)n2 + 2 * (size_t)n3 * nwr + 1;
+  floats += 2 * (size_t)(n3 + 1);   // twiddles of the LDS transforms
+  return floats * sizeof(float) + 16 * sizeof(double) + 16;
+}
+
+static int coop_threads(int n2, int n3) {
+  int m1 = 0;
+  switch (n3) {
+#define TCTF_CASE(n) case n: m1 = TubePlan<n>::M1; break;
+    TUBE_DFT_SIZES(TCTF_CASE)
+#undef TCTF_CASE
+    default: break;
+  }
+  const int n2p = (n2 + 63) / 64 * 64;
+  return (m1 > 0 && m1 * n2p <= 1024) ? m1 * n2p : 0;
 }
 
 void slice_set_attr(int n3, size_t lds) {
   if (lds <= 65536) return;
   switch (n3) {
-#define TCTF_CASE(n)                                                                                  \
-  case n:                                                                                             \
-    (void)hipFuncSetAttribute((const void*)k_slice<n>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+#define TCTF_CASE(n)                                                                                          \
+  case n:                                                                                                     \
+    (void)hipFuncSetAttribute((const void*)k_slice<n, SLICE_INIT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    (void)hipFuncSetAttribute((const void*)k_slice<n, SLICE_ITER>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    (void)hipFuncSetAttribute((const void*)k_slice<n, SLICE_RESULT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    (void)hipFuncSetAttribute((const void*)k_slice<n, SLICE_KKT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+    if constexpr (TubePlan<n>::M1 > 0) {                                                                      \
+      (void)hipFuncSetAttribute((const void*)k_slice_coop<n, SLICE_INIT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      (void)hipFuncSetAttribute((const void*)k_slice_coop<n, SLICE_ITER>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      (void)hipFuncSetAttribute((const void*)k_slice_coop<n, SLICE_RESULT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      (void)hipFuncSetAttribute((const void*)k_slice_coop<n, SLICE_KKT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    }                                                                                                         \
     break;
     TUBE_DFT_SIZES(TCTF_CASE)
 #undef TCTF_CASE
@@ -265,14 +644,35 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
   a.mode = mode;
   a.mixed = p.mixed;
   a.w_from_g = w_from_g;
+  const size_t lds = slice_lds_bytes(p.n2, p.n3);
+  const int coop = coop_threads(p.n2, p.n3);
+  if (coop > 0) {
+    switch (p.n3) {
+#define TCTF_CASE(n)                                                                                   \
+  case n:                                                                                              \
+    if constexpr (TubePlan<n>::M1 > 0) {                                                               \
+      if (mode == SLICE_INIT) k_slice_coop<n, SLICE_INIT><<<p.n1, coop, lds, p.stream>>>(a);           \
+      else if (mode == SLICE_ITER) k_slice_coop<n, SLICE_ITER><<<p.n1, coop, lds, p.stream>>>(a);      \
+      else if (mode == SLICE_RESULT) k_slice_coop<n, SLICE_RESULT><<<p.n1, coop, lds, p.stream>>>(a);  \
+      else k_slice_coop<n, SLICE_KKT><<<p.n1, coop, lds, p.stream>>>(a);                               \
+    }                                                                                                  \
+    break;
+      TUBE_DFT_SIZES(TCTF_CASE)
+#undef TCTF_CASE
+      default: break;
+    }
+    return;
+  }
   const int need = p.n2 > p.n3 ? p.n2 : p.n3;
   int threads = ((need + 63) / 64) * 64;
   if (threads > SLICE_THREADS) threads = SLICE_THREADS;
-  const size_t lds = slice_lds_bytes(p.n2, p.n3);
   switch (p.n3) {
 #define TCTF_CASE(n)                                                                   \
   case n:                                                                              \
-    k_slice<n><<<p.n1, threads, lds, p.stream>>>(a);                                   \
+    if (mode == SLICE_INIT) k_slice<n, SLICE_INIT><<<p.n1, threads, lds, p.stream>>>(a);        \
+    else if (mode == SLICE_ITER) k_slice<n, SLICE_ITER><<<p.n1, threads, lds, p.stream>>>(a);   \
+    else if (mode == SLICE_RESULT) k_slice<n, SLICE_RESULT><<<p.n1, threads, lds, p.stream>>>(a); \
+    else k_slice<n, SLICE_KKT><<<p.n1, threads, lds, p.stream>>>(a);                             \
     break;
     TUBE_DFT_SIZES(TCTF_CASE)
 #undef TCTF_CASE

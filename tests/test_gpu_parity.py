@@ -16,7 +16,7 @@ def _compare(g, st, info=None, tol=TOL, label=""):
     ez = rel(g["Z"], oracle.z_of(st))
     msg = f"{label} W {ew:.2e} Z {ez:.2e}"
     if info is not None and info["f0"]:
-        ef = abs(g["f0"][-1] - info["f0"][-1]) / abs(info["f0"][-1])
+        ef = abs(g["f0"][-1] - info["f0"][-1]) / max(abs(info["f0"][-1]), 1e-30)
         msg += f" f0 {ef:.2e}"
         assert ef <= tol, msg
     print(msg, flush=True)
