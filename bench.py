@@ -3,14 +3,22 @@
 
 A "step" is one full iteration of the method (X-step, Y-step, Z = X*Y, W-step and the
 tube transforms) over the synthetic 529 OD x 96 slot x 112 day traffic tensor (40 %
-sampled), with every input resident in device memory.  Both precisions are run:
-FP32 and mixed (BF16 W~ storage and BF16 slice-product operands, FP32 accumulation, FP64
-r x r Grams / pseudo-inverses / objective).  The equal-error protocol compares their
-completion error (RSE against the full synthetic tensor): FP32 after 200 iterations sets
-RSE32, and the mixed run's first iteration with RSE <= RSE32 (1 + 5e-3) is reported.
+sampled), with every input resident in device memory.  Both precisions are run: FP32, and
+mixed (W~ stored in BF16, factors FP32, FP32 accumulation; FP64 r x r Grams /
+pseudo-inverses / objective).  The equal-error protocol compares their completion error
+(RSE against the full synthetic tensor): FP32 after --rse-iters iterations sets RSE32, and
+the mixed run's first iteration with RSE <= RSE32 (1 + 5e-3) is reported (None if none).
+
+The dominant kernel's launches inside the timed steps are bracketed with HIP events on the
+library's stream; their mean duration and the kernel's algorithmic bytes give the roofline
+fraction.  HBM traffic measured with rocprofv3 counters is read from the summary under
+profiles/ when that summary was taken from the current kernel sources (else null).
 
 Prints ONE JSON line (metric, value = iterations/s of the headline precision, the
 roofline of the dominant kernel, the FP64 CPU oracle baseline, per-precision details).
+
+  --copy-calibration MIB   instead: run a plain device copy of MIB MiB five times (the
+                           reference kernel that scales the FETCH_SIZE / WRITE_SIZE counters)
 """
 from __future__ import annotations
 
@@ -55,19 +63,67 @@ def stage_bytes(stage, n1, n2, n3, r, mixed):
     }[stage]
 
 
+STAGE_NAMES = ("slice", "zgemm", "agemm", "hsolve", "bgemm", "ystep")
+# kernel symbol of each stage at this workload (what rocprofv3 lists)
+STAGE_KERNELS = {"slice": "k_slice_coop", "zgemm": "k_zgemm", "agemm": "k_agemm", "hsolve": "k_hsolve",
+                 "bgemm": "k_bgemm", "ystep": "k_ystep"}
+
+
 def run_precision(prec, d, w, steps, warmup, dev, torch):
+    """Warm up, time every stage over 20 iterations (to pick the dominant one), then time
+    `steps` iterations with only the dominant stage's launches bracketed by HIP events."""
     from paper_2005_09838_amd import Completion
     t = lambda a: torch.from_numpy(a).to(dev)
     c = Completion(t(d["G"]), t(d["omega"]), w.r, mu=w.mu, rho1=w.rho1, rho2=w.rho2, precision=prec,
                    X0=t(d["X0"]), Y0=t(d["Y0"]))
     c.step(warmup)
+    c.profile(STAGE_NAMES)          # every stage of 20 iterations, to find the dominant kernel
+    c.step(20)
+    stages = {name: us for name, (us, n) in c.profile_read().items()}
+    dominant = max(stages, key=stages.get)
+    c.profile([dominant])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     c.step(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stages = {name: c.time_stage(name, 20) for name in ("slice", "zgemm", "agemm", "hsolve", "bgemm", "ystep")}
-    return c, dt, stages
+    live_us, launches = c.profile_read()[dominant]
+    c.profile([])
+    return c, dt, stages, dominant, live_us, launches
+
+
+def measured_traffic(stage, prec):
+    """HBM bytes per launch from the rocprofv3 counter summary of this stage, or None when
+    there is none or it was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{stage}_{WORKLOAD}_{prec}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    from paper_2005_09838_amd.profile_summary import source_digest
+    if kv.get("source_sha256") != source_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib):
+    """A plain elementwise device copy of `mib` MiB (read once, written once), five times."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_kernel": "elementwise mul by 1.0", "bytes_read_per_launch": 4 * n,
+                      "bytes_written_per_launch": 4 * n, "launches": 5}), flush=True)
 
 
 def rse_history(prec, d, w, iters, every, dev, torch, M):
@@ -114,11 +170,17 @@ def main():
     ap.add_argument("--rse-iters", type=int, default=200)
     ap.add_argument("--oracle-iters", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--only", choices=("fp32", "mixed"), default=None,
+                    help="run one precision (no equal-error comparison); for counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs a completion on a single MI355X "
               "(--gpus 1); multi-GPU runs are not part of it.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import numpy as np
     import torch
@@ -130,19 +192,22 @@ def main():
     M = torch.from_numpy(d["M"]).to(dev)
     n1, n2, n3, r = w.n1, w.n2, w.n3, w.r
     res = {}
-    for prec in ("fp32", "mixed"):
-        c, dt, stages = run_precision(prec, d, w, args.steps, args.warmup, dev, torch)
+    precs = (args.only,) if args.only else ("fp32", "mixed")
+    for prec in precs:
+        c, dt, stages, dominant, live_us, launches = run_precision(prec, d, w, args.steps, args.warmup, dev,
+                                                                   torch)
         mixed = prec == "mixed"
         ips = args.steps / dt
         W = c.result()["W"]
         rse_end = float(torch.linalg.norm(W - M) / torch.linalg.norm(M))
-        dominant = max(stages, key=stages.get)
         res[prec] = {
             "iters_per_s": ips,
             "ms_per_step": 1000.0 * dt / args.steps,
             "hbm_gbps_algorithmic": algorithmic_bytes(n1, n2, n3, r, mixed) * ips / 1e9,
             "stage_us": {k: round(v, 3) for k, v in stages.items()},
             "dominant_kernel": dominant,
+            "dominant_live_us": live_us,
+            "dominant_live_launches": launches,
             "stage_gbps": {k: round(stage_bytes(k, n1, n2, n3, r, mixed) / (v * 1e-6) / 1e9, 1)
                            for k, v in stages.items()},
             "rse_after_timed_run": rse_end,
@@ -152,26 +217,28 @@ def main():
 
     # equal-error protocol
     every = 10
-    h32 = rse_history("fp32", d, w, args.rse_iters, every, dev, torch, M)
-    hmx = rse_history("mixed", d, w, args.rse_iters, every, dev, torch, M)
-    rse32 = h32[-1][1]
-    t_equal = next((it for it, v in hmx if v <= rse32 * (1 + 5e-3)), None)
-    res["fp32"]["rse"] = rse32
-    res["mixed"]["rse"] = hmx[-1][1]
-    res["mixed"]["rse_gap_rel"] = hmx[-1][1] / rse32 - 1.0
-    res["mixed"]["iters_to_fp32_rse"] = t_equal
-    res["fp32"]["rse_history"] = h32
-    res["mixed"]["rse_history"] = hmx
-    for prec in ("fp32", "mixed"):
-        it = args.rse_iters if prec == "fp32" else t_equal
-        res[prec]["seconds_to_fp32_rse"] = None if it is None else it / res[prec]["iters_per_s"]
+    t_equal = None
+    if len(precs) == 2 and args.rse_iters > 0:
+        h32 = rse_history("fp32", d, w, args.rse_iters, every, dev, torch, M)
+        hmx = rse_history("mixed", d, w, args.rse_iters, every, dev, torch, M)
+        rse32 = h32[-1][1]
+        t_equal = next((it for it, v in hmx if v <= rse32 * (1 + 5e-3)), None)
+        res["fp32"]["rse"] = rse32
+        res["mixed"]["rse"] = hmx[-1][1]
+        res["mixed"]["rse_gap_rel"] = hmx[-1][1] / rse32 - 1.0
+        res["mixed"]["iters_to_fp32_rse"] = t_equal
+        res["fp32"]["rse_history"] = h32
+        res["mixed"]["rse_history"] = hmx
+        for prec in ("fp32", "mixed"):
+            it = args.rse_iters if prec == "fp32" else t_equal
+            res[prec]["seconds_to_fp32_rse"] = None if it is None else it / res[prec]["iters_per_s"]
 
     # error against the FP64 oracle after the oracle's sample, and the CPU baseline
     cpu = None
     if not args.no_cpu and args.oracle_iters > 0:
         base = cpu_baseline(d, w, args.oracle_iters)
         st = base["one_core"]["state"]
-        for prec in ("fp32", "mixed"):
+        for prec in precs:
             from paper_2005_09838_amd import Completion
             t = lambda a: torch.from_numpy(a).to(dev)
             c = Completion(t(d["G"]), t(d["omega"]), r, mu=w.mu, rho1=w.rho1, rho2=w.rho2, precision=prec,
@@ -186,13 +253,15 @@ def main():
                "all_cores": {"value": base["all_cores"]["iters_per_s"], "cores": base["all_cores"]["cores"]}}
 
     # headline: the faster precision among those that reach the FP32 error
-    head = "fp32"
+    head = precs[0]
     if t_equal is not None and res["mixed"]["iters_per_s"] > res["fp32"]["iters_per_s"]:
         head = "mixed"
     hr = res[head]
     dom = hr["dominant_kernel"]
-    dom_us = hr["stage_us"][dom]
-    achieved = stage_bytes(dom, n1, n2, n3, r, head == "mixed") / (dom_us * 1e-6) / 1e9
+    dom_us = hr["dominant_live_us"]
+    dom_bytes = stage_bytes(dom, n1, n2, n3, r, head == "mixed")
+    achieved = dom_bytes / (dom_us * 1e-6) / 1e9
+    traffic = measured_traffic(dom, head)
     line = {
         "metric": "completion iters/s + HBM GB/s at 529x96x112 r=16, mixed vs FP32 at equal RSE",
         "value": round(hr["iters_per_s"], 2),
@@ -204,18 +273,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if head == "fp32" else "bf16-operands/f32-accumulate",
+        "dtype": "f32" if head == "fp32" else "bf16-storage/f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n1": n1, "n2": n2, "n3": n3, "r": r, "sampling": w.p,
                    "mu": w.mu, "rho1": w.rho1, "rho2": w.rho2, "headline_precision": head},
         "hbm_gbps": round(hr["hbm_gbps_algorithmic"], 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
-                     "kernel": f"{dom} ({head})", "kernel_us": round(dom_us, 3),
-                     "bytes_per_launch": stage_bytes(dom, n1, n2, n3, r, head == "mixed")},
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
+                     "kernel": f"{STAGE_KERNELS[dom]} ({dom}, {head})", "kernel_us": round(dom_us, 3),
+                     "launches_timed": hr["dominant_live_launches"], "bytes_per_launch": dom_bytes},
         "cpu_baseline": cpu,
         "precisions": {k: {kk: vv for kk, vv in v.items() if kk != "rse_history"} for k, v in res.items()},
-        "rse_history": {"fp32": res["fp32"]["rse_history"], "mixed": res["mixed"]["rse_history"]},
+        "rse_history": {k: v["rse_history"] for k, v in res.items() if "rse_history" in v},
     }
     print(json.dumps(line), flush=True)
 

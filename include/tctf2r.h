@@ -155,6 +155,16 @@ tctf_status tctf_complete(const tctf_params* p, const float* G, const uint8_t* o
  * Stages 0-5 recompute from the current state without advancing it (6 does advance). */
 tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* mean_us);
 
+/* Live per-stage timing of tctf_step.  tctf_profile(c, mask) with mask != 0 clears the
+ * record and, from then on, brackets every launch of each stage whose bit is set (bit k =
+ * stage k of tctf_time_stage, k = 0..5) with a pair of HIP events on the context's stream;
+ * mask = 0 stops recording and keeps the record.  Each pair adds two event records to the
+ * stream; the kernels themselves are unchanged.
+ * tctf_profile_read synchronises the stream and returns, per stage, the summed duration in
+ * microseconds of the recorded launches and their number. */
+tctf_status tctf_profile(tctf_ctx* c, uint32_t mask);
+tctf_status tctf_profile_read(tctf_ctx* c, double total_us[6], int64_t launches[6]);
+
 const char* tctf_status_string(tctf_status s);
 const char* tctf_last_error(void);  /* thread-local detail of the last failure */
 

@@ -7,10 +7,12 @@ from .binding import (STAGES, TCTF_FP32, TCTF_MIXED_BF16, Completion, TctfError,
                       make_params, tctf_complete, tctf_create, tctf_default_params, tctf_destroy,
                       tctf_get_result, tctf_get_state, tctf_iterations, tctf_last_error, tctf_objective,
                       tctf_params, tctf_set_state, tctf_state_bytes, tctf_stationarity, tctf_status_string,
-                      tctf_step, tctf_termination, tctf_time_stage, tctf_workspace_bytes)
+                      tctf_profile, tctf_profile_read, tctf_step, tctf_termination, tctf_time_stage,
+                      tctf_workspace_bytes)
 
 __all__ = ["STAGES", "TCTF_FP32", "TCTF_MIXED_BF16", "Completion", "TctfError", "complete", "library",
            "make_params", "tctf_complete", "tctf_create", "tctf_default_params", "tctf_destroy",
            "tctf_get_result", "tctf_get_state", "tctf_iterations", "tctf_last_error", "tctf_objective",
            "tctf_params", "tctf_set_state", "tctf_state_bytes", "tctf_stationarity", "tctf_status_string",
-           "tctf_step", "tctf_termination", "tctf_time_stage", "tctf_workspace_bytes"]
+           "tctf_profile", "tctf_profile_read", "tctf_step", "tctf_termination", "tctf_time_stage",
+           "tctf_workspace_bytes"]

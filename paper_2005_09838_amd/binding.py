@@ -61,6 +61,8 @@ def library() -> ctypes.CDLL:
         "tctf_destroy": (None, [P]),
         "tctf_complete": (I32, [PP, P, P, P, P, U64, I32, P, S, P, P, ctypes.POINTER(D)]),
         "tctf_time_stage": (I32, [P, I32, I32, ctypes.POINTER(D)]),
+        "tctf_profile": (I32, [P, ctypes.c_uint32]),
+        "tctf_profile_read": (I32, [P, ctypes.POINTER(D), ctypes.POINTER(I64)]),
         "tctf_status_string": (ctypes.c_char_p, [I32]),
         "tctf_last_error": (ctypes.c_char_p, []),
     }
@@ -170,6 +172,18 @@ def tctf_time_stage(ctx, stage: int, reps: int) -> float:
     v = ctypes.c_double()
     _check(library().tctf_time_stage(ctx, stage, reps, ctypes.byref(v)), "tctf_time_stage")
     return v.value
+
+
+def tctf_profile(ctx, mask: int) -> None:
+    _check(library().tctf_profile(ctx, mask), "tctf_profile")
+
+
+def tctf_profile_read(ctx):
+    """Per stage 0..5: (summed microseconds, launches) recorded since tctf_profile(ctx, mask)."""
+    tot = (ctypes.c_double * 6)()
+    cnt = (ctypes.c_int64 * 6)()
+    _check(library().tctf_profile_read(ctx, tot, cnt), "tctf_profile_read")
+    return [(tot[k], cnt[k]) for k in range(6)]
 
 
 def tctf_status_string(status: int) -> str:
@@ -289,6 +303,19 @@ class Completion:
 
     def time_stage(self, stage, reps=20):
         return tctf_time_stage(self.ctx, STAGES[stage] if isinstance(stage, str) else int(stage), reps)
+
+    def profile(self, stages):
+        """Bracket every launch of the named stages in later steps with HIP events (empty: stop)."""
+        mask = 0
+        for st in stages:
+            mask |= 1 << (STAGES[st] if isinstance(st, str) else int(st))
+        tctf_profile(self.ctx, mask)
+
+    def profile_read(self):
+        """{stage name: (mean microseconds per launch, launches)} of the recorded launches."""
+        names = {v: k for k, v in STAGES.items()}
+        return {names[k]: (tot / cnt if cnt else None, cnt)
+                for k, (tot, cnt) in enumerate(tctf_profile_read(self.ctx))}
 
 
 def complete(M, omega, r, lam=1e-2, rho1=1e-2, rho2=1e-2, iters=50, precision="fp32", X0=None, Y0=None,

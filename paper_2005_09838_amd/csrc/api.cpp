@@ -9,13 +9,14 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/tctf2r.h"
 #include "kernels.h"
 
 namespace tctf {
 size_t slice_lds_bytes(int n2, int n3);
-size_t ystep_lds_bytes(int r);
+size_t ystep_lds_bytes(int r, int n2);
 void slice_set_attr(int n3, size_t lds);
 void ystep_set_attr(size_t lds);
 }  // namespace tctf
@@ -117,6 +118,11 @@ struct tctf_ctx {
   int device;
   int64_t iters;
   bool term_valid;
+  // stage timing of tctf_step (tctf_profile): one event pair per profiled launch
+  uint32_t prof_mask = 0;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_stage;
+  size_t prof_used = 0;
 };
 
 static tctf_status validate(const tctf_params* p) {
@@ -210,14 +216,37 @@ static tctf_status check_launch() {
   return TCTF_OK;
 }
 
+// Launch one stage; when its bit is set in the profile mask, bracket it with two HIP events
+// on the context's stream (events come from a pool that grows as needed).
+extern "C++" template <typename F>
+static tctf_status stage(tctf_ctx* c, int id, F&& launch) {
+  if (!(c->prof_mask & (1u << id))) {
+    launch();
+    return TCTF_OK;
+  }
+  while (c->prof_used + 2 > c->prof_ev.size()) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    c->prof_ev.push_back(e);
+  }
+  HIP_TRY(hipEventRecord(c->prof_ev[c->prof_used], c->plan.stream));
+  launch();
+  HIP_TRY(hipEventRecord(c->prof_ev[c->prof_used + 1], c->plan.stream));
+  c->prof_stage.push_back(id);
+  c->prof_used += 2;
+  return TCTF_OK;
+}
+
 static tctf_status enqueue_iteration(tctf_ctx* c) {
   const Plan& p = c->plan;
-  tctf::launch_agemm(p);
-  tctf::launch_hsolve(p);
-  tctf::launch_bgemm(p);
-  tctf::launch_ystep(p, 0);
-  tctf::launch_zgemm(p);
-  tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0);
+  tctf_status s = TCTF_OK;
+  if (s == TCTF_OK) s = stage(c, 2, [&] { tctf::launch_agemm(p); });
+  if (s == TCTF_OK) s = stage(c, 3, [&] { tctf::launch_hsolve(p); });
+  if (s == TCTF_OK) s = stage(c, 4, [&] { tctf::launch_bgemm(p); });
+  if (s == TCTF_OK) s = stage(c, 5, [&] { tctf::launch_ystep(p, 0); });
+  if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p); });
+  if (s == TCTF_OK) s = stage(c, 0, [&] { tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0); });
+  if (s != TCTF_OK) return s;
   return check_launch();
 }
 
@@ -248,7 +277,7 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   fill_plan(c, (hipStream_t)hip_stream);
   const Plan& p = c->plan;
   tctf::slice_set_attr(p.n3, tctf::slice_lds_bytes(p.n2, p.n3));
-  tctf::ystep_set_attr(tctf::ystep_lds_bytes(p.r));
+  tctf::ystep_set_attr(tctf::ystep_lds_bytes(p.r, p.n2));
   tctf::launch_zero(p, p.flag, 64);
   tctf::launch_zero(p, p.qy_zero, (size_t)p.nb * 4);
   tctf::launch_pack_g(p, G, omega);
@@ -432,7 +461,38 @@ tctf_status tctf_iterations(tctf_ctx* c, int64_t* iters) {
   return TCTF_OK;
 }
 
-void tctf_destroy(tctf_ctx* c) { delete c; }
+void tctf_destroy(tctf_ctx* c) {
+  if (!c) return;
+  for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
+  delete c;
+}
+
+tctf_status tctf_profile(tctf_ctx* c, uint32_t mask) {
+  if (!c) return fail(TCTF_E_ARG, "context is NULL");
+  if (mask >> 6) return fail(TCTF_E_ARG, "profile mask 0x%x has bits beyond stage 5", mask);
+  if (mask) {
+    c->prof_used = 0;
+    c->prof_stage.clear();
+  }
+  c->prof_mask = mask;
+  return TCTF_OK;
+}
+
+tctf_status tctf_profile_read(tctf_ctx* c, double total_us[6], int64_t launches[6]) {
+  if (!c || !total_us || !launches) return fail(TCTF_E_ARG, "NULL argument");
+  for (int k = 0; k < 6; ++k) {
+    total_us[k] = 0.0;
+    launches[k] = 0;
+  }
+  HIP_TRY(hipStreamSynchronize(c->plan.stream));
+  for (size_t q = 0; q < c->prof_stage.size(); ++q) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->prof_ev[2 * q], c->prof_ev[2 * q + 1]));
+    total_us[c->prof_stage[q]] += 1000.0 * ms;
+    launches[c->prof_stage[q]] += 1;
+  }
+  return TCTF_OK;
+}
 
 tctf_status tctf_complete(const tctf_params* p, const float* G, const uint8_t* omega, const float* X0,
                           const float* Y0, uint64_t seed, int32_t iters, void* workspace, size_t ws_bytes,

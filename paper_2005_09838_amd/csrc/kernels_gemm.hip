@@ -69,10 +69,11 @@ __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, cons
                                                const cd* __restrict__ qy, const int* __restrict__ qy_zero,
                                                float2* __restrict__ rhs, int n1, int n2, int r, int nb,
                                                double eta, double rho1, int mixed, int raw_a) {
-  __shared__ float2 wsh[AG_ROWS][AG_COLS + 1];
-  __shared__ float2 ysh[TCTF_RMAX][AG_COLS + 1];
-  __shared__ cd gs[TCTF_RMAX * TCTF_RMAX];
-  __shared__ cd qs[TCTF_RMAX * TCTF_RMAX];
+  // 49.9 KB of LDS (three blocks per CU): the W~ and Y~ tiles; the epilogue reuses them
+  // for A (16 KB), G_Y^+ (16 KB) and Q_Y (16 KB).
+  __shared__ __align__(16) float2 smem[(AG_ROWS + TCTF_RMAX) * (AG_COLS + 1)];
+  float2 (*wsh)[AG_COLS + 1] = reinterpret_cast<float2 (*)[AG_COLS + 1]>(smem);
+  float2 (*ysh)[AG_COLS + 1] = reinterpret_cast<float2 (*)[AG_COLS + 1]>(smem + AG_ROWS * (AG_COLS + 1));
   const int i0 = blockIdx.x * AG_ROWS, b = blockIdx.y, tid = threadIdx.x;
   const int il = tid >> 2, q = tid & 3, i = i0 + il;
   constexpr int SP = TCTF_RMAX / 4;   // outputs per thread at most
@@ -132,16 +133,23 @@ __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, cons
     return;
   }
   const int noqy = qy_zero[b];
+  cd* gs = reinterpret_cast<cd*>(smem + AG_ROWS * TCTF_RMAX);
+  cd* qs = reinterpret_cast<cd*>(smem + AG_ROWS * (AG_COLS + 1));
+  static_assert(AG_ROWS * TCTF_RMAX * 2 <= AG_ROWS * (AG_COLS + 1), "A and G_Y^+ fit the W~ tile");
+  static_assert(TCTF_RMAX * TCTF_RMAX * 2 <= TCTF_RMAX * (AG_COLS + 1), "Q_Y fits the Y~ tile");
   for (int e = tid; e < r * r; e += 256) {
     gs[e] = gyp[(size_t)b * r * r + e];
     qs[e] = qy[(size_t)b * r * r + e];
   }
   __syncthreads();
-  float2* res = ash + AG_ROWS * TCTF_RMAX;   // [AG_ROWS][r] results, transposed store below
+  float2 res[SP];
   if (i < n1) {
     const double deg = (n1 == 1) ? 0.0 : ((i == 0 || i == n1 - 1) ? 1.0 : 2.0);
     const double dii = 1.0 + rho1 * deg;
-    for (int s = q; s < r; s += 4) {
+#pragma unroll
+    for (int us = 0; us < SP; ++us) {
+      const int s = q + 4 * us;
+      if (s >= r) break;
       cd t = cd_make(0.0, 0.0);
       for (int u = 0; u < r; ++u) {
         const float2 av = ash[il * r + u];
@@ -162,13 +170,21 @@ __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, cons
         // (H_rho1 U)_i = (1 + rho1 deg_i) U_i - rho1 (U_{i-1} + U_{i+1}); outside rows are 0
         t = cd_add(t, cd_sub(cd_scale(uu[1], dii), cd_scale(cd_add(uu[0], uu[2]), rho1)));
       }
-      res[il * r + s] = make_float2((float)t.re, (float)t.im);
+      res[us] = make_float2((float)t.re, (float)t.im);
+    }
+  }
+  __syncthreads();   // every thread has read A; its rows now take the results
+  if (i < n1) {
+#pragma unroll
+    for (int us = 0; us < SP; ++us) {
+      const int s = q + 4 * us;
+      if (s < r) ash[il * r + s] = res[us];
     }
   }
   __syncthreads();
   for (int e = tid; e < AG_ROWS * r; e += 256) {   // coalesced along i
     const int s = e / AG_ROWS, rr = e % AG_ROWS;
-    if (i0 + rr < n1) rhs[((size_t)b * r + s) * n1 + i0 + rr] = res[rr * r + s];
+    if (i0 + rr < n1) rhs[((size_t)b * r + s) * n1 + i0 + rr] = ash[rr * r + s];
   }
 }
 

@@ -90,53 +90,57 @@ void launch_tables(const Plan& p) {
 
 // Transform of eq. (bar BA-k) of real tubes src[p][q][0..n3) into stored frequencies
 // b = 0..n3/2: dst[b*sb + p*sp + q*sq] = sum_l exp(+2 pi i b l / n3) src[p][q][l].
-// Direct FP64 sums: used only to bring the initial factors into the Fourier domain.
+// Direct FP64 sums, one thread per (tube, frequency): used only to bring the initial
+// factors into the Fourier domain.
 __global__ void k_tube_dft_setup(const float* __restrict__ src, float2* __restrict__ dst, int P, int Q,
                                  int n3, int nb, long sb, long sp, long sq) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long)P * Q) return;
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (long)P * Q * nb) return;
+  const long t = g / nb;
+  const int b = (int)(g % nb);
   const long p = t / Q, q = t % Q;
   const float* a = src + t * n3;
-  for (int b = 0; b < nb; ++b) {
-    double re = 0.0, im = 0.0;
-    for (int l = 0; l < n3; ++l) {
-      double s, c;
-      sincospi(2.0 * (double)((long)b * l % n3) / n3, &s, &c);
-      re += c * a[l];
-      im += s * a[l];
-    }
-    if (bin_is_real(b, n3)) im = 0.0;
-    dst[b * sb + p * sp + q * sq] = make_float2((float)re, (float)im);
+  double re = 0.0, im = 0.0;
+  for (int l = 0; l < n3; ++l) {
+    double s, c;
+    sincospi(2.0 * (double)((long)b * l % n3) / n3, &s, &c);
+    re += c * a[l];
+    im += s * a[l];
   }
+  if (bin_is_real(b, n3)) im = 0.0;
+  dst[b * sb + p * sp + q * sq] = make_float2((float)re, (float)im);
 }
 
-// Inverse of eq. (barAAk) from the stored frequencies (conjugates fill the rest).
+// Inverse of eq. (barAAk) from the stored frequencies (conjugates fill the rest), one
+// thread per (tube, position).
 __global__ void k_tube_idft_setup(const float2* __restrict__ src, float* __restrict__ dst, int P, int Q,
                                   int n3, int nb, long sb, long sp, long sq) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long)P * Q) return;
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (long)P * Q * n3) return;
+  const long t = g / n3;
+  const int l = (int)(g % n3);
   const long p = t / Q, q = t % Q;
-  for (int l = 0; l < n3; ++l) {
-    double acc = 0.0;
-    for (int b = 0; b < nb; ++b) {
-      const float2 v = src[b * sb + p * sp + q * sq];
-      double s, c;
-      sincospi(2.0 * (double)((long)b * l % n3) / n3, &s, &c);
-      const double w = bin_weight(b, n3);
-      // Re(X_b exp(-i theta)) = re cos + im sin
-      acc += w * ((double)v.x * c + (bin_is_real(b, n3) ? 0.0 : (double)v.y * s));
-    }
-    dst[t * n3 + l] = (float)(acc / n3);
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const float2 v = src[b * sb + p * sp + q * sq];
+    double s, c;
+    sincospi(2.0 * (double)((long)b * l % n3) / n3, &s, &c);
+    const double w = bin_weight(b, n3);
+    // Re(X_b exp(-i theta)) = re cos + im sin
+    acc += w * ((double)v.x * c + (bin_is_real(b, n3) ? 0.0 : (double)v.y * s));
   }
+  dst[t * n3 + l] = (float)(acc / n3);
 }
 
 static inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 void launch_tube_dft_setup(const Plan& p, const float* src, float2* dst, int P, int Q, long sb, long sp, long sq) {
-  k_tube_dft_setup<<<blocks_for((long)P * Q, 128), 128, 0, p.stream>>>(src, dst, P, Q, p.n3, p.nb, sb, sp, sq);
+  k_tube_dft_setup<<<blocks_for((long)P * Q * p.nb, 256), 256, 0, p.stream>>>(src, dst, P, Q, p.n3, p.nb, sb,
+                                                                               sp, sq);
 }
 void launch_tube_idft_setup(const Plan& p, const float2* src, float* dst, int P, int Q, long sb, long sp, long sq) {
-  k_tube_idft_setup<<<blocks_for((long)P * Q, 128), 128, 0, p.stream>>>(src, dst, P, Q, p.n3, p.nb, sb, sp, sq);
+  k_tube_idft_setup<<<blocks_for((long)P * Q * p.n3, 256), 256, 0, p.stream>>>(src, dst, P, Q, p.n3, p.nb, sb,
+                                                                               sp, sq);
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the seed, counter = thread

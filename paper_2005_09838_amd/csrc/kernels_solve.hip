@@ -79,42 +79,70 @@ void launch_hsolve(const Plan& p) {
   k_hsolve<<<p.nb * p.r * 2, 64, lds, p.stream>>>(p.rhs, p.htab, p.xt, p.n1, p.r, p.n3);
 }
 
-// Dynamic LDS layout of k_ystep (r x r FP64 complex matrices unless noted).
+// Dynamic LDS layout of k_ystep (r x r FP64 complex matrices unless noted); jb columns of
+// Y~ are handled per block step.
+#define YS_THREADS 512
+#define YS_LDS_BUDGET (150 * 1024)
 struct YLayout {
-  size_t gx, dm, gp, q, work, vec, colk, rowk, rot, red, blk, yb, total;
+  size_t gx, dm, gp, q, gy, gpart, work, vec, colk, rowk, rot, red, bsum, yold, ynew, total;
 };
-__host__ __device__ inline YLayout ystep_layout(int r) {
+__host__ __device__ inline YLayout ystep_layout(int r, int jb) {
   YLayout L;
   const size_t m = (size_t)r * r * sizeof(cd);
+  const size_t npart = (size_t)(r * r < YS_THREADS ? YS_THREADS : r * r);
   size_t o = 0;
   L.gx = o; o += m;
   L.dm = o; o += m;
   L.gp = o; o += m;
   L.q = o; o += m;
+  L.gy = o; o += m;
+  L.gpart = o; o += npart * sizeof(cd);                 // partial Gram sums of one block step
   L.work = o; o += m;
   L.vec = o; o += m;
   L.colk = o; o += r * sizeof(cd);
   L.rowk = o; o += r * sizeof(cd);
   L.rot = o; o += 96 * sizeof(double);
   L.red = o; o += 16 * sizeof(double);
-  L.blk = o; o += (size_t)r * 32 * sizeof(cd);   // column block of X~^* W~ (FP64)
-  L.yb = o; o += (size_t)r * 32 * sizeof(cd);    // column block of the old Y~
+  // the column blocks below have a row stride of (jb | 1): odd, so the rows of one column
+  // fall in different LDS banks
+  const size_t ld = (size_t)(jb | 1);
+  L.bsum = o; o += (size_t)r * ld * sizeof(cd);         // columns of X~^* W~ (FP64)
+  L.yold = o; o += (size_t)r * ld * sizeof(float2);     // the same columns of the old Y~
+  L.ynew = o; o += (size_t)r * ld * sizeof(float2);     // and of the new (stored) Y~
   L.total = o;
   return L;
 }
 
-__global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const float2* __restrict__ bpart,
-                                               const cd* __restrict__ spart, const cd* __restrict__ dpart,
-                                               cd* __restrict__ gyp_out, cd* __restrict__ qy_out,
-                                               int* __restrict__ qy_zero, double* __restrict__ bin_obj,
-                                               int n2, int r, int n3, int nchunk, double eta, double rho1,
-                                               int force_eigen, int init) {
+// Columns per block step: all of n2 when they fit the LDS budget, else as many as fit.
+static int ystep_jb(int r, int n2) {
+  const size_t fixed = ystep_layout(r, 0).total;
+  const size_t per = (size_t)r * (sizeof(cd) + 2 * sizeof(float2));
+  int jb = (int)((YS_LDS_BUDGET - fixed) / per) - 1;
+  if (jb > n2) jb = n2;
+  if (jb < 1) jb = 1;
+  return jb;
+}
+
+// One block per frequency.  Y~ is visited in blocks of jb columns: the chunk partials of
+// X~^* W~ and the old columns are loaded together (independent loads, summed in a fixed
+// order), the new columns are formed in FP64 and stored in FP32, and their FP64 Gram is
+// accumulated from the stored values, so Y~ is read once and written once.  When a
+// pseudo-inverse keeps every eigenvalue and eta = 1, I - eta P is exactly 0 and is not
+// formed.
+__global__ void __launch_bounds__(YS_THREADS) k_ystep(float2* __restrict__ yt, const float2* __restrict__ bpart,
+                                                      const cd* __restrict__ spart, const cd* __restrict__ dpart,
+                                                      cd* __restrict__ gyp_out, cd* __restrict__ qy_out,
+                                                      int* __restrict__ qy_zero, double* __restrict__ bin_obj,
+                                                      int n2, int r, int n3, int nchunk, int jb, double eta,
+                                                      double rho1, int force_eigen, int init) {
   extern __shared__ __align__(16) unsigned char sm[];
-  const YLayout L = ystep_layout(r);
+  const YLayout L = ystep_layout(r, jb);
   cd* gx = (cd*)(sm + L.gx);
   cd* dm = (cd*)(sm + L.dm);
   cd* gp = (cd*)(sm + L.gp);
   cd* q = (cd*)(sm + L.q);
+  cd* gy = (cd*)(sm + L.gy);
+  cd* gpart = (cd*)(sm + L.gpart);
   PinvScratch ps;
   ps.work = (cd*)(sm + L.work);
   ps.vec = (cd*)(sm + L.vec);
@@ -122,96 +150,138 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const fl
   ps.rowk = (cd*)(sm + L.rowk);
   ps.rot = (double*)(sm + L.rot);
   ps.red = (double*)(sm + L.red);
-  cd* blk = (cd*)(sm + L.blk);
-  cd* yb = (cd*)(sm + L.yb);
-  const int b = blockIdx.x, tid = threadIdx.x, rr = r * r;
+  cd* bsum = (cd*)(sm + L.bsum);
+  float2* yold = (float2*)(sm + L.yold);
+  float2* ynew = (float2*)(sm + L.ynew);
+  const int b = blockIdx.x, tid = threadIdx.x, rr = r * r, nt = YS_THREADS;
   const bool real_bin = bin_is_real(b, n3);
 
   // G_X = S + rho1 D from the chunk partials (fixed order)
-  for (int e = tid; e < rr; e += 256) {
+  for (int e = tid; e < rr; e += nt) {
     cd sacc = cd_make(0.0, 0.0), dacc = cd_make(0.0, 0.0);
+#pragma unroll 4
     for (int c = 0; c < nchunk; ++c) {
       sacc = cd_add(sacc, spart[((size_t)b * nchunk + c) * rr + e]);
       dacc = cd_add(dacc, dpart[((size_t)b * nchunk + c) * rr + e]);
     }
     dm[e] = dacc;
     gx[e] = cd_add(sacc, cd_scale(dacc, rho1));
+    gy[e] = cd_make(0.0, 0.0);
   }
   __syncthreads();
 
+  bool qzero = true;
   if (!init) {
     const int full = pinv_herm(gx, gp, r, force_eigen, ps);
-    const bool qzero = full && eta == 1.0;
-    // q = I - eta G_X^+ G_X
-    for (int e = tid; e < rr; e += 256) {
-      const int s = e / r, t = e % r;
-      cd acc = cd_make(0.0, 0.0);
-      for (int u = 0; u < r; ++u) cd_fma(acc, gp[s * r + u], gx[u * r + t]);
-      q[e] = cd_make((s == t ? 1.0 : 0.0) - eta * acc.re, -eta * acc.im);
+    qzero = full && eta == 1.0;
+    if (!qzero) {   // q = I - eta G_X^+ G_X
+      for (int e = tid; e < rr; e += nt) {
+        const int s = e / r, t = e % r;
+        cd acc = cd_make(0.0, 0.0);
+        for (int u = 0; u < r; ++u) cd_fma(acc, gp[s * r + u], gx[u * r + t]);
+        q[e] = cd_make((s == t ? 1.0 : 0.0) - eta * acc.re, -eta * acc.im);
+      }
+      __syncthreads();
+    }
+  }
+  const int np = rr < nt ? nt / rr : 1;   // partial sums per Gram entry
+  const int ld = jb | 1;
+  for (int j0 = 0; j0 < n2; j0 += jb) {
+    const int nj = min(jb, n2 - j0), nel = r * nj;
+    for (int e0 = 0; e0 < nel; e0 += 4 * nt) {   // four elements per thread in flight
+      float2 y[4];
+      cd acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + tid + u * nt;
+        y[u] = make_float2(0.f, 0.f);
+        acc[u] = cd_make(0.0, 0.0);
+        if (e < nel) {
+          const int t = e / nj, jj = e % nj;
+          y[u] = yt[((size_t)b * r + t) * n2 + j0 + jj];
+          if (!init) {
+            const float2* bp = bpart + ((size_t)b * nchunk * r + t) * n2 + j0 + jj;
+#pragma unroll 8
+            for (int c = 0; c < nchunk; ++c) {
+              const float2 v = bp[(size_t)c * r * n2];
+              acc[u].re += v.x;
+              acc[u].im += v.y;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + tid + u * nt;
+        if (e < nel) {
+          const int t = e / nj, jj = e % nj;
+          yold[t * ld + jj] = y[u];
+          bsum[t * ld + jj] = acc[u];
+        }
+      }
     }
     __syncthreads();
-    // Y~ <- q Y~ + eta G_X^+ B, 32 columns at a time
-    for (int j0 = 0; j0 < n2; j0 += 32) {
-      const int nj = min(32, n2 - j0);
-      for (int e = tid; e < r * 32; e += 256) {
-        const int t = e >> 5, jj = e & 31;
-        if (jj < nj) {
-          cd acc = cd_make(0.0, 0.0);
-          for (int c = 0; c < nchunk; ++c) {
-            const float2 v = bpart[(((size_t)b * nchunk + c) * r + t) * n2 + j0 + jj];
-            acc.re += v.x;
-            acc.im += v.y;
+    if (!init) {
+      // Y~ <- q Y~ + eta G_X^+ B on these columns
+      for (int e = tid; e < nel; e += nt) {
+        const int s = e / nj, jj = e % nj;
+        cd acc = cd_make(0.0, 0.0), acc2 = cd_make(0.0, 0.0);
+#pragma unroll 4
+        for (int t = 0; t < r; ++t) cd_fma(acc2, gp[s * r + t], bsum[t * ld + jj]);
+        if (!qzero) {
+#pragma unroll 4
+          for (int t = 0; t < r; ++t) {
+            const float2 y = yold[t * ld + jj];
+            cd_fma(acc, q[s * r + t], cd_make(y.x, y.y));
           }
-          blk[t * 32 + jj] = acc;
-          const float2 y = yt[((size_t)b * r + t) * n2 + j0 + jj];
-          yb[t * 32 + jj] = cd_make(y.x, y.y);
         }
-      }
-      __syncthreads();
-      for (int e = tid; e < r * 32; e += 256) {
-        const int s = e >> 5, jj = e & 31;
-        if (jj < nj) {
-          cd acc = cd_make(0.0, 0.0), acc2 = cd_make(0.0, 0.0);
-          for (int t = 0; t < r; ++t) cd_fma(acc2, gp[s * r + t], blk[t * 32 + jj]);
-          if (!qzero)
-            for (int t = 0; t < r; ++t) cd_fma(acc, q[s * r + t], yb[t * 32 + jj]);
-          acc = cd_add(acc, cd_scale(acc2, eta));
-          yt[((size_t)b * r + s) * n2 + j0 + jj] = make_float2((float)acc.re, real_bin ? 0.0f : (float)acc.im);
-        }
+        acc = cd_add(acc, cd_scale(acc2, eta));
+        const float2 v = make_float2((float)acc.re, real_bin ? 0.0f : (float)acc.im);
+        ynew[s * ld + jj] = v;
+        yt[((size_t)b * r + s) * n2 + j0 + jj] = v;
       }
       __syncthreads();
     }
+    // G_Y += (stored columns) (stored columns)^*, np interleaved partial sums per entry
+    const float2* yb = init ? yold : ynew;
+    for (int e2 = tid; e2 < rr * np; e2 += nt) {
+      const int e = e2 % rr, part = e2 / rr, s = e / r, t = e % r;
+      cd acc = cd_make(0.0, 0.0);
+#pragma unroll 4
+      for (int jj = part; jj < nj; jj += np) {
+        const float2 u = yb[s * ld + jj], v = yb[t * ld + jj];
+        cd_fma(acc, cd_make(u.x, u.y), cd_make(v.x, -v.y));
+      }
+      gpart[e2] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < rr; e += nt) {
+      cd acc = gy[e];
+      for (int part = 0; part < np; ++part) acc = cd_add(acc, gpart[part * rr + e]);
+      gy[e] = acc;
+    }
+    __syncthreads();
   }
 
-  // G_Y = Y~ Y~^* of the stored (FP32) Y~, its pseudo-inverse and q = I - eta G_Y G_Y^+
-  for (int e = tid; e < rr; e += 256) {
-    const int s = e / r, t = e % r;
-    const float2* ys = yt + ((size_t)b * r + s) * n2;
-    const float2* ytt = yt + ((size_t)b * r + t) * n2;
-    cd acc = cd_make(0.0, 0.0);
-    for (int j = 0; j < n2; ++j) {
-      const float2 u = ys[j], v = ytt[j];
-      cd_fma(acc, cd_make(u.x, u.y), cd_make(v.x, -v.y));
-    }
-    gx[e] = acc;
-  }
-  __syncthreads();
-  const int fully = pinv_herm(gx, gp, r, force_eigen, ps);
+  // the pseudo-inverse of G_Y and q = I - eta G_Y G_Y^+ for the next X-update
+  const int fully = pinv_herm(gy, gp, r, force_eigen, ps);
   const bool qyz = fully && eta == 1.0;
-  for (int e = tid; e < rr; e += 256) {
-    const int s = e / r, t = e % r;
-    cd acc = cd_make(0.0, 0.0);
-    for (int u = 0; u < r; ++u) cd_fma(acc, gx[s * r + u], gp[u * r + t]);
-    q[e] = cd_make((s == t ? 1.0 : 0.0) - eta * acc.re, -eta * acc.im);
+  for (int e = tid; e < rr; e += nt) {
+    cd qv = cd_make(0.0, 0.0);
+    if (!qyz) {
+      const int s = e / r, t = e % r;
+      cd acc = cd_make(0.0, 0.0);
+      for (int u = 0; u < r; ++u) cd_fma(acc, gy[s * r + u], gp[u * r + t]);
+      qv = cd_make((s == t ? 1.0 : 0.0) - eta * acc.re, -eta * acc.im);
+    }
+    qy_out[(size_t)b * rr + e] = qv;
     gyp_out[(size_t)b * rr + e] = gp[e];
   }
-  __syncthreads();
-  for (int e = tid; e < rr; e += 256) qy_out[(size_t)b * rr + e] = q[e];
   // c_b tr(D G_Y): the rho1 term of eq. (fun-XYW) for this frequency
   double tr = 0.0;
-  for (int e = tid; e < rr; e += 256) {
+  for (int e = tid; e < rr; e += nt) {
     const int s = e / r, t = e % r;
-    const cd d = dm[s * r + t], g = gx[t * r + s];
+    const cd d = dm[s * r + t], g = gy[t * r + s];
     tr += d.re * g.re - d.im * g.im;
   }
   tr = block_sum_d(tr, ps.red);
@@ -221,7 +291,7 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const fl
   }
 }
 
-size_t ystep_lds_bytes(int r) { return ystep_layout(r).total; }
+size_t ystep_lds_bytes(int r, int n2) { return ystep_layout(r, ystep_jb(r, n2)).total; }
 
 void ystep_set_attr(size_t lds) {
   if (lds > 65536)
@@ -229,9 +299,11 @@ void ystep_set_attr(size_t lds) {
 }
 
 void launch_ystep(const Plan& p, int init) {
-  const size_t lds = ystep_lds_bytes(p.r);
-  k_ystep<<<p.nb, 256, lds, p.stream>>>(p.yt, p.bpart, p.spart, p.dpart, p.gyp, p.qy, p.qy_zero, p.bin_obj,
-                                        p.n2, p.r, p.n3, p.nchunk, p.eta, p.rho1, p.force_eigen, init);
+  const int jb = ystep_jb(p.r, p.n2);
+  const size_t lds = ystep_layout(p.r, jb).total;
+  k_ystep<<<p.nb, YS_THREADS, lds, p.stream>>>(p.yt, p.bpart, p.spart, p.dpart, p.gyp, p.qy, p.qy_zero,
+                                               p.bin_obj, p.n2, p.r, p.n3, p.nchunk, jb, p.eta, p.rho1,
+                                               p.force_eigen, init);
 }
 
 }  // namespace tctf

@@ -4,10 +4,12 @@
 //
 // Rule: eigenvalues lambda_i <= tau = r * eps64 * lambda_max are dropped (a zero matrix
 // gives 0).  Fast path: Gauss-Jordan elimination (the sweep operator, no pivoting, valid
-// for positive-definite input).  Its result is accepted only if it proves that every
-// eigenvalue exceeds 8 tau:  lambda_min >= 1/||A^-1||_F > 8 r eps ||A||_F >= 8 tau.
-// Then the rule keeps every eigenvalue and A^+ = A^-1.  Otherwise (or when forced) a
-// cyclic Jacobi eigen-decomposition with parallel (round-robin) pair ordering is used
+// for positive-definite input); for r <= 16 the first wavefront runs it alone with the
+// matrix in registers, for larger r the block runs it in LDS.  Its result
+// is accepted only if it proves that every eigenvalue exceeds 8 tau:
+// lambda_min >= 1/||A^-1||_F > 8 r eps ||A||_F >= 8 tau.  Then the rule keeps every
+// eigenvalue and A^+ = A^-1.  Otherwise (or when forced) a cyclic Jacobi
+// eigen-decomposition with parallel (round-robin) pair ordering is used by the whole block
 // and the rule is applied to its eigenvalues.
 #pragma once
 #include "common.h"
@@ -23,9 +25,98 @@ struct PinvScratch {
   double* red; // >= 16 doubles
 };
 
+// Wavefront-level fast path for r <= 16 (called by the 64 lanes of one wavefront).  The
+// matrix, padded with the identity to 16 x 16, lives in registers: lane l holds row
+// l / 4, columns 4 (l % 4) .. 4 (l % 4) + 3.  Pivot row, pivot column and pivot reach the
+// lanes by cross-lane shuffles.
+// Returns 1: accepted, P = A^-1;  2: A is not finite, P = NaN;  3: A has no positive
+// diagonal entry (the zero PSD matrix), P = 0;  0: rejected, P untouched.
+__device__ inline int pinv_gj_wave16(const cd* A, cd* P, int r) {
+  const int lane = threadIdx.x & 63, p = lane >> 2, q0 = (lane & 3) * 4, rr = r * r;
+  double vr[4], vi[4];
+  double f2 = 0.0, dmax = -1.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = q0 + i;
+    if (p < r && q < r) {
+      const cd a = A[p * r + q];
+      vr[i] = a.re;
+      vi[i] = a.im;
+      f2 += a.re * a.re + a.im * a.im;
+      if (p == q) dmax = fmax(dmax, a.re);
+    } else {
+      vr[i] = (p == q) ? 1.0 : 0.0;
+      vi[i] = 0.0;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    f2 += __shfl_xor(f2, off);
+    dmax = fmax(dmax, __shfl_xor(dmax, off));
+  }
+  if (!isfinite(f2)) {
+    for (int e = lane; e < rr; e += 64) P[e] = cd_make(NAN, NAN);
+    return 2;
+  }
+  if (!(dmax > 0.0)) {
+    for (int e = lane; e < rr; e += 64) P[e] = cd_make(0.0, 0.0);
+    return 3;
+  }
+  bool ok = true;
+  for (int k = 0; k < r; ++k) {
+    const int ks = k & 3, src_row = 4 * k + (lane & 3), src_col = 4 * p + (k >> 2);
+    double wr[4], wi[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      wr[i] = __shfl(vr[i], src_row);   // (k, q0 + i)
+      wi[i] = __shfl(vi[i], src_row);
+    }
+    const double ownr = ks == 0 ? vr[0] : ks == 1 ? vr[1] : ks == 2 ? vr[2] : vr[3];
+    const double owni = ks == 0 ? vi[0] : ks == 1 ? vi[1] : ks == 2 ? vi[2] : vi[3];
+    const double cr = __shfl(ownr, src_col), ci = __shfl(owni, src_col);   // (p, k)
+    const double piv = __shfl(ownr, 4 * k + (k >> 2));                      // (k, k)
+    ok = ok && piv > 0.0;   // the same in every lane; a failed pivot rejects the result
+    const double ip = piv > 0.0 ? 1.0 / piv : 0.0;
+    const bool isrow = p == k;
+    // branch-free update: pivot -> -1/piv, pivot row -> w/piv, pivot column -> c/piv,
+    // elsewhere v - c w / piv
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool iscol = q0 + i == k;
+      const double gr = vr[i] - (cr * wr[i] - ci * wi[i]) * ip;
+      const double gi = vi[i] - (cr * wi[i] + ci * wr[i]) * ip;
+      const double nr = isrow ? (iscol ? -ip : wr[i] * ip) : (iscol ? cr * ip : gr);
+      const double ni = isrow ? (iscol ? 0.0 : wi[i] * ip) : (iscol ? ci * ip : gi);
+      vr[i] = nr;
+      vi[i] = ni;
+    }
+  }
+  if (!ok) return 0;
+  double g2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (p < r && q0 + i < r) g2 += vr[i] * vr[i] + vi[i] * vi[i];
+  for (int off = 32; off > 0; off >>= 1) g2 += __shfl_xor(g2, off);
+  if (!(isfinite(g2) && 8.0 * r * TCTF_EPS64 * sqrt(f2) * sqrt(g2) < 1.0)) return 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (p < r && q0 + i < r) P[p * r + q0 + i] = cd_make(-vr[i], -vi[i]);
+  return 1;
+}
+
 // Returns 1 (to every thread) if all eigenvalues were kept, 0 otherwise.
 __device__ inline int pinv_herm(const cd* A, cd* P, int r, int force_eigen, PinvScratch s) {
   const int tid = threadIdx.x, nt = blockDim.x, rr = r * r;
+  if (!force_eigen && r <= 16) {
+    if (tid < 64) {
+      const int f = pinv_gj_wave16(A, P, r);
+      if (tid == 0) s.rot[0] = (double)f;
+    }
+    __syncthreads();
+    const int f = (int)s.rot[0];
+    __syncthreads();
+    if (f == 1) return 1;
+    if (f == 2 || f == 3) return 0;
+  }
   double f2 = 0.0, dmax = -1.0;
   for (int e = tid; e < rr; e += nt) {
     cd a = A[e];
@@ -46,7 +137,7 @@ __device__ inline int pinv_herm(const cd* A, cd* P, int r, int force_eigen, Pinv
   }
   const double fro = sqrt(f2);
 
-  if (!force_eigen) {
+  if (!force_eigen && r > 16) {   // block-level Gauss-Jordan for the larger ranks
     for (int e = tid; e < rr; e += nt) s.work[e] = A[e];
     __syncthreads();
     bool ok = true;

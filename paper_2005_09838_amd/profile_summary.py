@@ -1,0 +1,152 @@
+"""Condense rocprofv3 CSV output into the short text summaries kept with the measurements.
+
+  python -m paper_2005_09838_amd.profile_summary stats DIR --command CMD --out FILE
+      kernel table (calls, mean / min / max duration, share of GPU time) from the
+      *kernel_stats.csv that `rocprofv3 --kernel-trace --stats --output-format csv` wrote.
+
+  python -m paper_2005_09838_amd.profile_summary traffic --fetch DIR --write DIR
+         --copy-fetch DIR --copy-write DIR --kernel NAME --copy-bytes N --stage S
+         --precision P --workload W --algorithmic-bytes B --command CMD --out FILE
+      HBM traffic of one kernel per launch: the mean FETCH_SIZE and WRITE_SIZE per dispatch
+      (KiB) of the kernel, each scaled by the ratio of the known bytes of a plain copy
+      kernel to what the same counter reads for it.  The summary records the SHA-256 of the
+      kernel sources it was taken from, so a later reader can tell whether it still applies.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import statistics
+from collections import defaultdict
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def source_digest() -> str:
+    """SHA-256 over the library's kernel sources (the generated tube transforms excluded)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name == "tube_dft_gen.h" or not name.endswith((".hip", ".cpp", ".h", ".py")):
+            continue
+        h.update(name.encode())
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _find(directory: str, suffix: str) -> list[str]:
+    """The newest *suffix file under directory (one profiled process per directory)."""
+    out = glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True)
+    if not out:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    return [max(out, key=os.path.getmtime)]
+
+
+def _short(name: str) -> str:
+    """Drop the argument list and namespace of a demangled kernel name."""
+    base = name.split("(")[0].strip()
+    if base.startswith("void "):
+        base = base[5:]
+    return base.replace("tctf::", "")
+
+
+def kernel_stats(directory: str):
+    rows = []
+    for path in _find(directory, "kernel_stats.csv"):
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def write_stats(directory: str, command: str, out: str) -> None:
+    rows = kernel_stats(directory)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["rocprofv3 kernel statistics", f"command: {command}", "",
+             f"{'kernel':58s} {'calls':>7s} {'mean_us':>9s} {'min_us':>9s} {'max_us':>9s} {'share%':>7s}"]
+    for r in rows:
+        lines.append(f"{_short(r['Name'])[:58]:58s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['MinNs']) / 1e3:9.2f} {float(r['MaxNs']) / 1e3:9.2f} {float(r['Percentage']):7.2f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def counter_means(directory: str, counter: str):
+    """{kernel name: (mean counter value per dispatch, dispatches)}."""
+    vals = defaultdict(list)
+    for path in _find(directory, "counter_collection.csv"):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") == counter:
+                    vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: (statistics.fmean(v), len(v)) for k, v in vals.items()}
+
+
+def _pick(means, pattern: str):
+    """The kernel whose name contains `pattern` with the most dispatches."""
+    cands = [(n, k, m) for k, (m, n) in means.items() if pattern in k]
+    if not cands:
+        raise SystemExit(f"no dispatch of a kernel matching {pattern!r}")
+    n, k, m = max(cands)
+    return k, m, n
+
+
+def write_traffic(a) -> None:
+    kib = 1024.0
+    fk, fetch, fn = _pick(counter_means(a.fetch, "FETCH_SIZE"), a.kernel)
+    wk, write, wn = _pick(counter_means(a.write, "WRITE_SIZE"), a.kernel)
+    _, cfetch, _ = _pick(counter_means(a.copy_fetch, "FETCH_SIZE"), a.copy_kernel)
+    _, cwrite, _ = _pick(counter_means(a.copy_write, "WRITE_SIZE"), a.copy_kernel)
+    f_fetch = a.copy_bytes / (cfetch * kib)
+    f_write = a.copy_bytes / (cwrite * kib)
+    fetch_b = fetch * kib * f_fetch
+    write_b = write * kib * f_write
+    lines = [
+        f"HBM traffic of the {a.stage} kernel ({a.precision}) at {a.workload}",
+        f"kernel: {_short(fk)}",
+        f"source_sha256: {source_digest()}",
+        f"fetch_kib_per_dispatch: {fetch:.1f}",
+        f"fetch_dispatches: {fn}",
+        f"write_kib_per_dispatch: {write:.1f}",
+        f"write_dispatches: {wn}",
+        f"copy_fetch_kib_per_dispatch: {cfetch:.1f}",
+        f"copy_write_kib_per_dispatch: {cwrite:.1f}",
+        f"copy_bytes_each_way: {a.copy_bytes}",
+        f"fetch_scale: {f_fetch:.4f}",
+        f"write_scale: {f_write:.4f}",
+        f"fetch_bytes_per_launch: {fetch_b:.0f}",
+        f"write_bytes_per_launch: {write_b:.0f}",
+        f"traffic_bytes_per_launch: {fetch_b + write_b:.0f}",
+        f"algorithmic_bytes_per_launch: {a.algorithmic_bytes}",
+        f"traffic_over_algorithmic: {(fetch_b + write_b) / a.algorithmic_bytes:.3f}",
+        "commands:",
+    ] + [f"  {c}" for c in a.command]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("directory")
+    s.add_argument("--command", required=True)
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "stage", "precision", "workload", "out"):
+        t.add_argument("--" + k.replace("_", "-"), required=True)
+    t.add_argument("--copy-kernel", default="elementwise")
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--algorithmic-bytes", type=float, required=True)
+    t.add_argument("--command", action="append", required=True)
+    a = ap.parse_args()
+    if a.what == "stats":
+        write_stats(a.directory, a.command, a.out)
+    else:
+        write_traffic(a)
+
+
+if __name__ == "__main__":
+    main()

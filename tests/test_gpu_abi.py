@@ -94,3 +94,18 @@ def test_mixed_precision_tracks_fp32():
     print(f"RSE fp32 {rse_a:.5f} mixed {rse_b:.5f} W rel diff {rel(b['W'], a['W']):.2e}", flush=True)
     assert np.all(np.isfinite(b["W"]))
     assert abs(rse_b - rse_a) <= 0.05 * rse_a
+
+
+def test_stage_profile_records_each_launch():
+    """tctf_profile brackets exactly the launches of the chosen stages; results are unchanged."""
+    d = make_inputs(40, 30, 12, 4, p=0.4, seed=8)
+    a = gpu_run(d, 4, 6)
+    b = gpu_run(d, 4, 2)
+    c = b["ctx"]
+    c.profile(["slice", "bgemm"])
+    c.step(4)
+    rec = c.profile_read()
+    assert rec["slice"][1] == 4 and rec["bgemm"][1] == 4 and rec["agemm"][1] == 0
+    assert rec["slice"][0] > 0 and rec["bgemm"][0] > 0
+    c.profile([])
+    assert np.array_equal(c.result()["W"].cpu().numpy(), a["W"].astype(np.float32))
