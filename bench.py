@@ -9,9 +9,9 @@ pseudo-inverses / objective).  The equal-error protocol compares their completio
 (RSE against the full synthetic tensor): FP32 after --rse-iters iterations sets RSE32, and
 the mixed run's first iteration with RSE <= RSE32 (1 + 5e-3) is reported (None if none).
 
-The dominant kernel's launches inside the timed steps are bracketed with HIP events on the
-library's stream; their mean duration and the kernel's algorithmic bytes give the roofline
-fraction.  HBM traffic measured with rocprofv3 counters is read from the summary under
+After the timed steps, as many steps again run with the dominant kernel's launches
+bracketed by HIP events on the library's stream; their mean duration and the kernel's
+algorithmic bytes give the roofline fraction.  HBM traffic measured with rocprofv3 counters is read from the summary under
 profiles/ when that summary was taken from the current kernel sources (else null).
 
 Prints ONE JSON line (metric, value = iterations/s of the headline precision, the
@@ -70,23 +70,28 @@ STAGE_KERNELS = {"slice": "k_slice_coop", "zgemm": "k_zgemm", "agemm": "k_agemm"
 
 
 def run_precision(prec, d, w, steps, warmup, dev, torch):
-    """Warm up, time every stage over 20 iterations (to pick the dominant one), then time
-    `steps` iterations with only the dominant stage's launches bracketed by HIP events."""
+    """Warm up; time every stage over 20 iterations (to pick the dominant one); time `steps`
+    iterations as the library runs them (graph replays); then `steps` more with only the
+    dominant stage's launches bracketed by HIP events on the library's stream (event
+    recording makes those launches eager, which changes the gaps between kernels, not the
+    kernels)."""
     from paper_2005_09838_amd import Completion
     t = lambda a: torch.from_numpy(a).to(dev)
     c = Completion(t(d["G"]), t(d["omega"]), w.r, mu=w.mu, rho1=w.rho1, rho2=w.rho2, precision=prec,
                    X0=t(d["X0"]), Y0=t(d["Y0"]))
     c.step(warmup)
-    c.profile(STAGE_NAMES)          # every stage of 20 iterations, to find the dominant kernel
+    c.profile(STAGE_NAMES)
     c.step(20)
     stages = {name: us for name, (us, n) in c.profile_read().items()}
     dominant = max(stages, key=stages.get)
-    c.profile([dominant])
+    c.profile([])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     c.step(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    c.profile([dominant])
+    c.step(steps)
     live_us, launches = c.profile_read()[dominant]
     c.profile([])
     return c, dt, stages, dominant, live_us, launches
@@ -211,7 +216,7 @@ def main():
             "stage_gbps": {k: round(stage_bytes(k, n1, n2, n3, r, mixed) / (v * 1e-6) / 1e9, 1)
                            for k, v in stages.items()},
             "rse_after_timed_run": rse_end,
-            "iterations_at_rse": args.warmup + args.steps,
+            "iterations_at_rse": args.warmup + 20 + 2 * args.steps,
         }
         c.close()
 

@@ -103,7 +103,10 @@ tctf_status tctf_create(const tctf_params* p, const float* G, const uint8_t* ome
                         void* workspace, size_t ws_bytes, void* hip_stream, tctf_ctx** out);
 
 /* Enqueue `iters` iterations (steps 1-4 and 7 of the algorithm box; step 5 keeps r,
- * step 6 is tctf_termination).  Asynchronous and stream-ordered. */
+ * step 6 is tctf_termination).  Asynchronous and stream-ordered.  Whole blocks of 10
+ * iterations are replayed from a HIP graph that the first call needing one captures on a
+ * private stream of the context (the results are the same as eager launches); while
+ * tctf_profile is recording, every launch is eager. */
 tctf_status tctf_step(tctf_ctx* c, int32_t iters);
 
 /* Synchronise and return f0 of eq. (TETP-optim) at the current iterate, accumulated in

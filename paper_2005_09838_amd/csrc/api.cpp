@@ -63,7 +63,7 @@ static void chunking(int n1, int nb, int* nchunk, int* chunk) {
   int want = (512 + nb - 1) / nb;
   int maxc = (n1 + 31) / 32;
   int nc = want < maxc ? want : maxc;
-  const int minc = (n1 + 191) / 192;   // at most 192 rows per chunk (LDS of the Gram partials)
+  const int minc = (n1 + 63) / 64;   // at most 64 rows per chunk (the staged W~ slab)
   if (nc < minc) nc = minc;
   if (nc < 1) nc = 1;
   int ch = (n1 + nc - 1) / nc;
@@ -123,7 +123,14 @@ struct tctf_ctx {
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_stage;
   size_t prof_used = 0;
+  // GRAPH_ITERS iterations captured once as a HIP graph (on a private stream) and replayed
+  // on the context's stream
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
 };
+
+#define GRAPH_ITERS 10
 
 static tctf_status validate(const tctf_params* p) {
   if (!p) return fail(TCTF_E_ARG, "params is NULL");
@@ -278,6 +285,7 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   const Plan& p = c->plan;
   tctf::slice_set_attr(p.n3, tctf::slice_lds_bytes(p.n2, p.n3));
   tctf::ystep_set_attr(tctf::ystep_lds_bytes(p.r, p.n2));
+  tctf::bgemm_set_attr(tctf::bgemm_lds_bytes(p.r, p.chunk));
   tctf::launch_zero(p, p.flag, 64);
   tctf::launch_zero(p, p.qy_zero, (size_t)p.nb * 4);
   tctf::launch_pack_g(p, G, omega);
@@ -311,11 +319,49 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   return TCTF_OK;
 }
 
+// Capture GRAPH_ITERS iterations into a graph (once per context).  The kernels take the
+// same buffers every iteration, so one graph serves every later call.
+static tctf_status ensure_graph(tctf_ctx* c) {
+  if (c->graph_exec) return TCTF_OK;
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const hipStream_t user = c->plan.stream;
+  c->plan.stream = c->cap_stream;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  tctf_status s = TCTF_OK;
+  if (e == hipSuccess) {
+    for (int k = 0; k < GRAPH_ITERS && s == TCTF_OK; ++k) s = enqueue_iteration(c);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->cap_stream, &g);
+    if (e == hipSuccess) {
+      c->graph = g;
+      e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    }
+  }
+  c->plan.stream = user;
+  if (s != TCTF_OK) return s;
+  if (e != hipSuccess) {
+    c->graph_exec = nullptr;
+    return fail(TCTF_E_HIP, "graph capture of the iteration: %s", hipGetErrorString(e));
+  }
+  return TCTF_OK;
+}
+
 tctf_status tctf_step(tctf_ctx* c, int32_t iters) {
   if (!c) return fail(TCTF_E_ARG, "context is NULL");
   if (iters < 0) return fail(TCTF_E_ARG, "iters must be >= 0");
   const Plan& p = c->plan;
-  for (int32_t it = 0; it < iters; ++it) {
+  int32_t it = 0;
+  // whole blocks of GRAPH_ITERS iterations as graph replays (not while stages are being
+  // timed); the last iteration always runs eagerly after the termination snapshot
+  if (c->prof_mask == 0 && iters - 1 >= GRAPH_ITERS) {
+    tctf_status s = ensure_graph(c);
+    if (s != TCTF_OK) return s;
+    for (; iters - 1 - it >= GRAPH_ITERS; it += GRAPH_ITERS) {
+      HIP_TRY(hipGraphLaunch(c->graph_exec, p.stream));
+      c->iters += GRAPH_ITERS;
+    }
+  }
+  for (; it < iters; ++it) {
     if (it == iters - 1) {
       const size_t welem = tctf::wt_elem_bytes(p);
       HIP_TRY(hipMemcpyAsync(p.xt_prev, p.xt, (size_t)p.nb * p.r * p.n1 * 8, hipMemcpyDeviceToDevice, p.stream));
@@ -464,6 +510,12 @@ tctf_status tctf_iterations(tctf_ctx* c, int64_t* iters) {
 void tctf_destroy(tctf_ctx* c) {
   if (!c) return;
   for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
+  if (c->graph_exec) {
+    (void)hipStreamSynchronize(c->plan.stream);   // no replay of the graph may be in flight
+    hipGraphExecDestroy(c->graph_exec);
+  }
+  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   delete c;
 }
 

@@ -81,6 +81,31 @@ __device__ __forceinline__ double block_sum_d(double v, double* red) {
   __syncthreads();
   return s;
 }
+// Three block-wide FP64 sums at once (blockDim.x <= 1024; red holds >= 48 doubles).
+__device__ __forceinline__ void block_sum3_d(double& a, double& b, double& c, double* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+    c += __shfl_xor(c, off);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[wid] = a;
+    red[16 + wid] = b;
+    red[32 + wid] = c;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0, sc = 0.0;
+  for (int w = 0; w < nw; ++w) {   // fixed order
+    sa += red[w];
+    sb += red[16 + w];
+    sc += red[32 + w];
+  }
+  a = sa;
+  b = sb;
+  c = sc;
+}
 __device__ __forceinline__ double block_max_d(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
@@ -91,4 +116,44 @@ __device__ __forceinline__ double block_max_d(double v, double* red) {
   for (int w = 1; w < nw; ++w) s = fmax(s, red[w]);
   __syncthreads();
   return s;
+}
+
+// Block-cooperative copy of n elements, dst[e] = load(e) for e < n, in batches of PER
+// elements per thread whose loads are all issued before any of their stores (a loop of
+// load-then-store would wait out one memory latency per element).
+template <int PER, typename T, typename F>
+__device__ __forceinline__ void stage_batched(T* dst, int n, F load) {
+  const int nt = blockDim.x;
+  for (int e0 = 0; e0 < n; e0 += PER * nt) {
+    T v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = e0 + threadIdx.x + u * nt;
+      if (e < n) v[u] = load(e);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = e0 + threadIdx.x + u * nt;
+      if (e < n) dst[e] = v[u];
+    }
+  }
+}
+
+// The same with a store functor: store(e, value) for e < n.
+template <int PER, typename T, typename L, typename S>
+__device__ __forceinline__ void stage_batched_to(int n, L load, S store) {
+  const int nt = blockDim.x;
+  for (int e0 = 0; e0 < n; e0 += PER * nt) {
+    T v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = e0 + threadIdx.x + u * nt;
+      if (e < n) v[u] = load(e);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = e0 + threadIdx.x + u * nt;
+      if (e < n) store(e, v[u]);
+    }
+  }
 }

@@ -59,6 +59,8 @@ void launch_zgemm(const Plan& p);
 void launch_agemm(const Plan& p, int raw_a = 0);
 void launch_hsolve(const Plan& p);
 void launch_bgemm(const Plan& p);
+size_t bgemm_lds_bytes(int r, int chunk);
+void bgemm_set_attr(size_t lds);
 void launch_ystep(const Plan& p, int init);
 void launch_objective(const Plan& p);
 void launch_termination(const Plan& p);

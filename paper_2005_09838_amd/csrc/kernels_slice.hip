@@ -563,9 +563,7 @@ __global__ void __launch_bounds__(1024) k_slice_coop(SliceArgs a) {
       a.kkt[3 * i + 2] = sm;
     }
   } else if constexpr (MODE != SLICE_RESULT) {
-    fit = block_sum_d(fit, red);
-    ridge = block_sum_d(ridge, red);
-    sm = block_sum_d(sm, red);
+    block_sum3_d(fit, ridge, sm, red);
     if (tid == 0) {
       a.slice_obj[3 * i + 0] = fit;
       a.slice_obj[3 * i + 1] = ridge;
@@ -588,7 +586,7 @@ size_t slice_lds_bytes(int n2, int n3) {
   const size_t ld = (n3 % 2 == 0) ? n3 + 3 : n3 + 2;
   size_t floats = (size_t)n2 * ld + 4 * (size_t)n2 + 2 * (size_t)n3 * nwr + 1;
   floats += 2 * (size_t)(n3 + 1);   // twiddles of the LDS transforms
-  return floats * sizeof(float) + 16 * sizeof(double) + 16;
+  return floats * sizeof(float) + 48 * sizeof(double) + 16;
 }
 
 static int coop_threads(int n2, int n3) {

@@ -109,3 +109,21 @@ def test_stage_profile_records_each_launch():
     assert rec["slice"][0] > 0 and rec["bgemm"][0] > 0
     c.profile([])
     assert np.array_equal(c.result()["W"].cpu().numpy(), a["W"].astype(np.float32))
+
+
+def test_graph_replays_match_eager_launches():
+    """Blocks of iterations replayed from the captured graph give the same bits as eager
+    launches, across several replays separated by eager work and synchronisations."""
+    d = make_inputs(45, 37, 14, 5, p=0.35, seed=17)
+    g = gpu_run(d, 5, 0)
+    e = gpu_run(d, 5, 0)
+    cg, ce = g["ctx"], e["ctx"]
+    ce.profile(["slice"])   # recording stages forces eager launches
+    for k in (23, 11, 30):
+        cg.step(k)          # graph replays + eager remainder
+        ce.step(k)
+        wg = cg.result()["W"].cpu().numpy()
+        we = ce.result()["W"].cpu().numpy()
+        assert np.array_equal(wg, we), k
+        assert cg.objective() == ce.objective()
+    ce.profile([])
