@@ -60,13 +60,14 @@ def stage_bytes(stage, n1, n2, n3, r, mixed):
         "hsolve": 2 * fx,                                # read the right-hand side, write X~
         "bgemm": sw * nh + fx + fy,                      # read W~ and X~, write X~^* W~
         "ystep": 2 * fy,                                 # read and write Y~
+        "pinvy": 3 * 16 * nb * r * r,                    # read G_Y, write G_Y^+ and I - eta P_Y
     }[stage]
 
 
-STAGE_NAMES = ("slice", "zgemm", "agemm", "hsolve", "bgemm", "ystep")
+STAGE_NAMES = ("slice", "zgemm", "agemm", "hsolve", "bgemm", "ystep", "pinvy")
 # kernel symbol of each stage at this workload (what rocprofv3 lists)
-STAGE_KERNELS = {"slice": "k_slice_coop", "zgemm": "k_zgemm", "agemm": "k_agemm", "hsolve": "k_hsolve",
-                 "bgemm": "k_bgemm", "ystep": "k_ystep"}
+STAGE_KERNELS = {"slice": "k_slice_coop", "zgemm": "k_zgemm", "agemm": "k_agemm", "hsolve": "k_hsolve_reg",
+                 "bgemm": "k_bgemm", "ystep": "k_ystep", "pinvy": "k_pinvy"}
 
 
 def run_precision(prec, d, w, steps, warmup, dev, torch):

@@ -105,8 +105,7 @@ tctf_status tctf_create(const tctf_params* p, const float* G, const uint8_t* ome
 /* Enqueue `iters` iterations (steps 1-4 and 7 of the algorithm box; step 5 keeps r,
  * step 6 is tctf_termination).  Asynchronous and stream-ordered.  Whole blocks of 10
  * iterations are replayed from a HIP graph that the first call needing one captures on a
- * private stream of the context (the results are the same as eager launches); while
- * tctf_profile is recording, every launch is eager. */
+ * private stream of the context (the results are the same as eager launches). */
 tctf_status tctf_step(tctf_ctx* c, int32_t iters);
 
 /* Synchronise and return f0 of eq. (TETP-optim) at the current iterate, accumulated in
@@ -153,20 +152,20 @@ tctf_status tctf_complete(const tctf_params* p, const float* G, const uint8_t* o
  * stream between two HIP events and return the mean duration in microseconds.  Stages:
  *   0 slice kernel (inverse tube transform, W-step, forward transform; the W~ stream)
  *   1 Z~ = X~Y~ products        2 A = W~Y~^* products and the X right-hand side
- *   3 tridiagonal H_rho1 solve  4 X~^* W~ and Gram partials     5 Y-step and Grams
- *   6 one whole iteration
- * Stages 0-5 recompute from the current state without advancing it (6 does advance). */
+ *   3 tridiagonal H_rho1 solve  4 X~^* W~ and Gram partials     5 Y-step and G_Y
+ *   6 pseudo-inverse of G_Y     7 one whole iteration
+ * Stages 0-6 recompute from the current state without advancing it (7 does advance). */
 tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* mean_us);
 
 /* Live per-stage timing of tctf_step.  tctf_profile(c, mask) with mask != 0 clears the
  * record and, from then on, brackets every launch of each stage whose bit is set (bit k =
- * stage k of tctf_time_stage, k = 0..5) with a pair of HIP events on the context's stream;
- * mask = 0 stops recording and keeps the record.  Each pair adds two event records to the
- * stream; the kernels themselves are unchanged.
+ * stage k of tctf_time_stage, k = 0..6) with a pair of HIP events on the context's stream;
+ * mask = 0 stops recording and keeps the record.  While recording, every launch is eager
+ * (no graph replay); the kernels themselves are unchanged.
  * tctf_profile_read synchronises the stream and returns, per stage, the summed duration in
  * microseconds of the recorded launches and their number. */
 tctf_status tctf_profile(tctf_ctx* c, uint32_t mask);
-tctf_status tctf_profile_read(tctf_ctx* c, double total_us[6], int64_t launches[6]);
+tctf_status tctf_profile_read(tctf_ctx* c, double total_us[7], int64_t launches[7]);
 
 const char* tctf_status_string(tctf_status s);
 const char* tctf_last_error(void);  /* thread-local detail of the last failure */

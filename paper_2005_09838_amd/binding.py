@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libtctf2r.so")
 
 TCTF_OK, TCTF_E_ARG, TCTF_E_SHAPE, TCTF_E_NONFINITE, TCTF_E_HIP, TCTF_E_WORKSPACE, TCTF_E_STATE = 0, -1, -2, -3, -4, -5, -6
 TCTF_FP32, TCTF_MIXED_BF16 = 0, 1
-STAGES = {"slice": 0, "zgemm": 1, "agemm": 2, "hsolve": 3, "bgemm": 4, "ystep": 5, "iteration": 6}
+STAGES = {"slice": 0, "zgemm": 1, "agemm": 2, "hsolve": 3, "bgemm": 4, "ystep": 5, "pinvy": 6, "iteration": 7}
 
 
 class tctf_params(ctypes.Structure):
@@ -179,11 +179,11 @@ def tctf_profile(ctx, mask: int) -> None:
 
 
 def tctf_profile_read(ctx):
-    """Per stage 0..5: (summed microseconds, launches) recorded since tctf_profile(ctx, mask)."""
-    tot = (ctypes.c_double * 6)()
-    cnt = (ctypes.c_int64 * 6)()
+    """Per stage 0..6: (summed microseconds, launches) recorded since tctf_profile(ctx, mask)."""
+    tot = (ctypes.c_double * 7)()
+    cnt = (ctypes.c_int64 * 7)()
     _check(library().tctf_profile_read(ctx, tot, cnt), "tctf_profile_read")
-    return [(tot[k], cnt[k]) for k in range(6)]
+    return [(tot[k], cnt[k]) for k in range(7)]
 
 
 def tctf_status_string(status: int) -> str:

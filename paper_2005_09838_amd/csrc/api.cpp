@@ -51,7 +51,7 @@ struct StateHeader {
 };
 
 struct Layout {
-  size_t gp, wt, zt, xt, yt, rhs, bpart, spart, dpart, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
+  size_t gp, wt, zt, xt, yt, rhs, bpart, spart, dpart, gym, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
       flag, scal, xt_prev, yt_prev, wt_prev, stat_work, kkt, total;
   size_t state_bytes;
 };
@@ -90,6 +90,7 @@ static Layout make_layout(const tctf_params& p) {
   L.bpart = take(nb * nchunk * r * n2 * 8);
   L.spart = take(nb * nchunk * r * r * 16);
   L.dpart = take(nb * nchunk * r * r * 16);
+  L.gym = take(nb * r * r * 16);
   L.gyp = take(nb * r * r * 16);
   L.qy = take(nb * r * r * 16);
   L.qy_zero = take(nb * 4);
@@ -201,6 +202,7 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.bpart = (float2*)(w + L.bpart);
   q.spart = (cd*)(w + L.spart);
   q.dpart = (cd*)(w + L.dpart);
+  q.gym = (cd*)(w + L.gym);
   q.gyp = (cd*)(w + L.gyp);
   q.qy = (cd*)(w + L.qy);
   q.qy_zero = (int*)(w + L.qy_zero);
@@ -251,6 +253,7 @@ static tctf_status enqueue_iteration(tctf_ctx* c) {
   if (s == TCTF_OK) s = stage(c, 3, [&] { tctf::launch_hsolve(p); });
   if (s == TCTF_OK) s = stage(c, 4, [&] { tctf::launch_bgemm(p); });
   if (s == TCTF_OK) s = stage(c, 5, [&] { tctf::launch_ystep(p, 0); });
+  if (s == TCTF_OK) s = stage(c, 6, [&] { tctf::launch_pinvy(p, p.stream); });
   if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p); });
   if (s == TCTF_OK) s = stage(c, 0, [&] { tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0); });
   if (s != TCTF_OK) return s;
@@ -278,7 +281,7 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   c->term_valid = false;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
-    delete c;
+    delete c;   // nothing created yet
     return fail(TCTF_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
   }
   fill_plan(c, (hipStream_t)hip_stream);
@@ -302,17 +305,18 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   tctf::launch_slice(p, tctf::SLICE_INIT, nullptr, nullptr, 1);
   tctf::launch_bgemm(p);
   tctf::launch_ystep(p, 1);
+  tctf::launch_pinvy(p, p.stream);
   s = check_launch();
-  if (s != TCTF_OK) { delete c; return s; }
+  if (s != TCTF_OK) { tctf_destroy(c); return s; }
   int flag = 0;
   e = hipMemcpyAsync(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost, p.stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
   if (e != hipSuccess) {
-    delete c;
+    tctf_destroy(c);
     return fail(TCTF_E_HIP, "create: %s", hipGetErrorString(e));
   }
   if (flag) {
-    delete c;
+    tctf_destroy(c);
     return fail(TCTF_E_NONFINITE, "an observed value of G is NaN or Inf");
   }
   *out = c;
@@ -516,12 +520,13 @@ void tctf_destroy(tctf_ctx* c) {
   }
   if (c->graph) hipGraphDestroy(c->graph);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+
   delete c;
 }
 
 tctf_status tctf_profile(tctf_ctx* c, uint32_t mask) {
   if (!c) return fail(TCTF_E_ARG, "context is NULL");
-  if (mask >> 6) return fail(TCTF_E_ARG, "profile mask 0x%x has bits beyond stage 5", mask);
+  if (mask >> 7) return fail(TCTF_E_ARG, "profile mask 0x%x has bits beyond stage 6", mask);
   if (mask) {
     c->prof_used = 0;
     c->prof_stage.clear();
@@ -530,9 +535,9 @@ tctf_status tctf_profile(tctf_ctx* c, uint32_t mask) {
   return TCTF_OK;
 }
 
-tctf_status tctf_profile_read(tctf_ctx* c, double total_us[6], int64_t launches[6]) {
+tctf_status tctf_profile_read(tctf_ctx* c, double total_us[7], int64_t launches[7]) {
   if (!c || !total_us || !launches) return fail(TCTF_E_ARG, "NULL argument");
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < 7; ++k) {
     total_us[k] = 0.0;
     launches[k] = 0;
   }
@@ -562,7 +567,7 @@ tctf_status tctf_complete(const tctf_params* p, const float* G, const uint8_t* o
 
 tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* mean_us) {
   if (!c || !mean_us) return fail(TCTF_E_ARG, "NULL argument");
-  if (stage < 0 || stage > 6 || reps < 1) return fail(TCTF_E_ARG, "stage must be 0..6 and reps >= 1");
+  if (stage < 0 || stage > 7 || reps < 1) return fail(TCTF_E_ARG, "stage must be 0..7 and reps >= 1");
   const Plan& p = c->plan;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -576,7 +581,8 @@ tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* me
       case 3: tctf::launch_hsolve(p); break;
       case 4: tctf::launch_bgemm(p); break;
       case 5: tctf::launch_ystep(p, 1); break;
-      case 6: enqueue_iteration(c); c->iters++; break;
+      case 6: tctf::launch_pinvy(p, p.stream); break;
+      case 7: enqueue_iteration(c); c->iters++; break;
     }
   }
   HIP_TRY(hipEventRecord(e1, p.stream));

@@ -23,6 +23,7 @@ struct Plan {
   float2* bpart;    // partial X~^* W~ [nb][nchunk][r][n2]
   cd* spart;        // partial X~^* X~  [nb][nchunk][r][r]
   cd* dpart;        // partial (H X~)^* (H X~) [nb][nchunk][r][r]
+  cd* gym;          // Y~ Y~^* [nb][r][r]
   cd* gyp;          // (Y~ Y~^*)^+ [nb][r][r]
   cd* qy;           // I - eta P_Y [nb][r][r]
   int* qy_zero;     // [nb] 1 when I - eta P_Y is exactly 0 (eta = 1, full rank)
@@ -62,6 +63,7 @@ void launch_bgemm(const Plan& p);
 size_t bgemm_lds_bytes(int r, int chunk);
 void bgemm_set_attr(size_t lds);
 void launch_ystep(const Plan& p, int init);
+void launch_pinvy(const Plan& p, hipStream_t stream);
 void launch_objective(const Plan& p);
 void launch_termination(const Plan& p);
 void launch_stationarity(const Plan& p, int w_from_g);

@@ -15,11 +15,16 @@
 namespace tctf {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 // D += A B on one 16 x 16 x 4 FP32 tile: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16], and holds D[4 (l / 16) + t][l % 16] in element t.
 __device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// The FP64 16 x 16 x 4 tile: operands as above; lane l holds D[l / 16 + 4 t][l % 16].
+__device__ __forceinline__ v4d mfma4d(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 // Two consecutive complex entries of W~ (j, j + 1) as four floats; entries past the end read 0.
@@ -423,41 +428,52 @@ __global__ void __launch_bounds__(256) k_bgemm(const void* __restrict__ wt, cons
       }
     }
   }
-  // Gram partials of the chunk (FP64): X~^* X~ and (H X~)^*(H X~) over its rows; each
-  // entry sums four interleaved row sets (independent chains), joined in a fixed order
+  // Gram partials of the chunk in FP64 on the matrix cores: C = X'^T X' and the same for the
+  // row differences X'(i + 1) - X'(i) (rows whose successor exists), 2r x 2r real tiles of
+  // 16 x 16 over K = the chunk's rows; then X~^* X~ (s, t) = (C[2s][2t] + C[2s+1][2t+1],
+  // C[2s][2t+1] - C[2s+1][2t]) and the same for (H X~)^*(H X~).
+  __syncthreads();   // the W~ slab area is free: the tiles go there
+  double* cs = (double*)ws;                 // [2 RM][2 RM]
+  double* cdm = cs + 4 * RM * RM;           // [2 RM][2 RM]
+  for (int tile = w; tile < MT * MT; tile += 4) {
+    const int ta = tile / MT, tb = tile % MT;
+    v4d accs = v4d{0.0, 0.0, 0.0, 0.0}, accd = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; ks < nks; ++ks) {
+      const int kr = 4 * ks + q;              // chunk row of this lane's K index
+      const bool in = kr < nrows, hasnext = in && i0 + kr + 1 < n1;
+      const int ca = 16 * ta + m, cb = 16 * tb + m;   // columns 2 s + d of X'
+      const bool va = ca < 2 * r, vb = cb < 2 * r;
+      const float* x0 = xs + (size_t)kr * xld;
+      const double a0 = (in && va) ? (double)x0[ca] : 0.0, b0 = (in && vb) ? (double)x0[cb] : 0.0;
+      const double a1 = (hasnext && va) ? (double)x0[xld + ca] - a0 : 0.0;
+      const double b1 = (hasnext && vb) ? (double)x0[xld + cb] - b0 : 0.0;
+      accs = mfma4d(a0, b0, accs);
+      accd = mfma4d(a1, b1, accd);
+    }
+    // element t of the FP64 tile is row 16 ta + q + 4 t, column 16 tb + m
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int rw = 16 * ta + q + 4 * t, cl = 16 * tb + m;
+      cs[rw * 2 * RM + cl] = accs[t];
+      cdm[rw * 2 * RM + cl] = accd[t];
+    }
+  }
   __syncthreads();
   for (int e = tid; e < r * r; e += 256) {
     const int s = e / r, t = e % r;
-    cd sacc[4], dacc2[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      sacc[k] = cd_make(0.0, 0.0);
-      dacc2[k] = cd_make(0.0, 0.0);
-    }
-    for (int i = i0; i < i1; i += 4) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (i + k < i1) {
-          const float* xr = xs + (size_t)(i + k - i0) * xld;
-          const cd xsv = cd_make(xr[2 * s], xr[2 * s + 1]), xtv = cd_make(xr[2 * t], xr[2 * t + 1]);
-          cd_fma(sacc[k], cd_conj(xsv), xtv);
-          if (i + k + 1 < n1) {
-            const float* xn = xr + xld;
-            const cd ds = cd_make((double)xn[2 * s] - xsv.re, (double)xn[2 * s + 1] - xsv.im);
-            const cd dt = cd_make((double)xn[2 * t] - xtv.re, (double)xn[2 * t + 1] - xtv.im);
-            cd_fma(dacc2[k], cd_conj(ds), dt);
-          }
-        }
-      }
-    }
-    spart[(((size_t)b * nchunk + c) * r) * r + e] = cd_add(cd_add(sacc[0], sacc[1]), cd_add(sacc[2], sacc[3]));
+    const int r0 = 2 * s * 2 * RM, r1 = (2 * s + 1) * 2 * RM;
+    spart[(((size_t)b * nchunk + c) * r) * r + e] =
+        cd_make(cs[r0 + 2 * t] + cs[r1 + 2 * t + 1], cs[r0 + 2 * t + 1] - cs[r1 + 2 * t]);
     dpart[(((size_t)b * nchunk + c) * r) * r + e] =
-        cd_add(cd_add(dacc2[0], dacc2[1]), cd_add(dacc2[2], dacc2[3]));
+        cd_make(cdm[r0 + 2 * t] + cdm[r1 + 2 * t + 1], cdm[r0 + 2 * t + 1] - cdm[r1 + 2 * t]);
   }
 }
 
 size_t bgemm_lds_bytes(int r, int chunk) {
-  return ((size_t)(chunk + 1) * (2 * r + 16) + (size_t)((chunk + 3) / 4 * 4) * BG_WLD) * sizeof(float);
+  const int rm = r <= 8 ? 8 : (r <= 16 ? 16 : 32);
+  const size_t slab = (size_t)((chunk + 3) / 4 * 4) * BG_WLD * sizeof(float);
+  const size_t tiles = 2 * (size_t)(2 * rm) * (2 * rm) * sizeof(double);   // the FP64 Gram tiles
+  return (size_t)(chunk + 1) * (2 * r + 16) * sizeof(float) + (slab > tiles ? slab : tiles);
 }
 
 void bgemm_set_attr(size_t lds) {

@@ -9,8 +9,9 @@
 //
 // k_ystep: per frequency, the Y-update (second line of eq. (updataXYW1)):
 //   G_X = X~^* H_rho1 X~ = X~^* X~ + rho1 (H X~)^*(H X~),  Y~ <- (I - eta P_X) Y~ + eta G_X^+ X~^* W~,
-//   with P_X = G_X^+ G_X; then the Gram of the new Y~, its pseudo-inverse and I - eta P_Y
-//   for the next X-update, and the Fourier-domain H term of the objective.  FP64 throughout.
+//   with P_X = G_X^+ G_X; then the Gram of the new Y~ and the Fourier-domain H term of the
+//   objective.  FP64 throughout.
+// k_pinvy: the pseudo-inverse of that Gram and I - eta P_Y for the next X-update.
 #include "kernels.h"
 #include "pinv.h"
 
@@ -74,7 +75,96 @@ __global__ void __launch_bounds__(64) k_hsolve(const float2* __restrict__ rhs, c
   for (int i = lane; i < n1; i += 64) out[2 * (size_t)i] = col[i];
 }
 
+// The same solve with one wavefront per complex column (H_rho1 is real, so the real and
+// imaginary parts share every coefficient) and everything in registers: lane l holds rows
+// [l L, l L + L) of the column and their coefficients, L = ceil(n1 / 64) <= HS_L.  All loads
+// of a lane are issued before the recurrences.
+#define HS_L 16
+__global__ void __launch_bounds__(64) k_hsolve_reg(const float2* __restrict__ rhs, const float* __restrict__ htab,
+                                                   float2* __restrict__ xt, int n1, int r, int n3) {
+  const int c = blockIdx.x, lane = threadIdx.x;   // complex column c = b r + s
+  const int b = c / r;
+  const float2* in = rhs + (size_t)c * n1;
+  float2* out = xt + (size_t)c * n1;
+  const int L = (n1 + 63) / 64, st = min(n1, lane * L), en = min(n1, st + L);
+  float2 v[HS_L];
+  float lf[HS_L], ia[HS_L], bk[HS_L];
+#pragma unroll
+  for (int u = 0; u < HS_L; ++u) {
+    const int i = st + u;
+    const bool ok = i < en;
+    v[u] = ok ? in[i] : make_float2(0.f, 0.f);
+    lf[u] = ok ? htab[i] : 1.0f;           // rho1 / alpha_{i-1}
+    ia[u] = ok ? htab[n1 + i] : 0.0f;      // 1 / alpha_i
+    bk[u] = ok ? htab[2 * n1 + i] : 1.0f;  // rho1 / alpha_i
+  }
+  // forward: y_i = t_i + l_i y_{i-1}
+  float a = 1.0f, cr = 0.0f, ci = 0.0f;
+#pragma unroll
+  for (int u = 0; u < HS_L; ++u) {
+    if (st + u < en) {
+      cr = fmaf(lf[u], cr, v[u].x);
+      ci = fmaf(lf[u], ci, v[u].y);
+      a *= lf[u];
+      v[u] = make_float2(cr, ci);
+    }
+  }
+  for (int d = 1; d < 64; d <<= 1) {
+    const float a2 = __shfl_up(a, d), r2 = __shfl_up(cr, d), i2 = __shfl_up(ci, d);
+    if (lane >= d) {
+      cr = fmaf(a, r2, cr);
+      ci = fmaf(a, i2, ci);
+      a *= a2;
+    }
+  }
+  float yr = __shfl_up(cr, 1), yi = __shfl_up(ci, 1);
+  if (lane == 0) yr = yi = 0.0f;
+  float pr = 1.0f;
+#pragma unroll
+  for (int u = 0; u < HS_L; ++u) {
+    if (st + u < en) {
+      pr *= lf[u];
+      v[u] = make_float2(fmaf(pr, yr, v[u].x), fmaf(pr, yi, v[u].y));
+    }
+  }
+  // backward: x_i = y_i / alpha_i + (rho1 / alpha_i) x_{i+1}
+  a = 1.0f;
+  cr = ci = 0.0f;
+#pragma unroll
+  for (int u = HS_L - 1; u >= 0; --u) {
+    if (st + u < en) {
+      cr = fmaf(bk[u], cr, ia[u] * v[u].x);
+      ci = fmaf(bk[u], ci, ia[u] * v[u].y);
+      a *= bk[u];
+      v[u] = make_float2(cr, ci);
+    }
+  }
+  for (int d = 1; d < 64; d <<= 1) {
+    const float a2 = __shfl_down(a, d), r2 = __shfl_down(cr, d), i2 = __shfl_down(ci, d);
+    if (lane + d < 64) {
+      cr = fmaf(a, r2, cr);
+      ci = fmaf(a, i2, ci);
+      a *= a2;
+    }
+  }
+  float xr = __shfl_down(cr, 1), xi = __shfl_down(ci, 1);
+  if (lane == 63) xr = xi = 0.0f;
+  pr = 1.0f;
+  const bool real_bin = bin_is_real(b, n3);
+#pragma unroll
+  for (int u = HS_L - 1; u >= 0; --u) {
+    if (st + u < en) {
+      pr *= bk[u];
+      out[st + u] = make_float2(fmaf(pr, xr, v[u].x), real_bin ? 0.0f : fmaf(pr, xi, v[u].y));
+    }
+  }
+}
+
 void launch_hsolve(const Plan& p) {
+  if (p.n1 <= 64 * HS_L) {
+    k_hsolve_reg<<<p.nb * p.r, 64, 0, p.stream>>>(p.rhs, p.htab, p.xt, p.n1, p.r, p.n3);
+    return;
+  }
   const size_t lds = (size_t)p.n1 * sizeof(float);
   k_hsolve<<<p.nb * p.r * 2, 64, lds, p.stream>>>(p.rhs, p.htab, p.xt, p.n1, p.r, p.n3);
 }
@@ -131,8 +221,7 @@ static int ystep_jb(int r, int n2) {
 // formed.
 __global__ void __launch_bounds__(YS_THREADS) k_ystep(float2* __restrict__ yt, const float2* __restrict__ bpart,
                                                       const cd* __restrict__ spart, const cd* __restrict__ dpart,
-                                                      cd* __restrict__ gyp_out, cd* __restrict__ qy_out,
-                                                      int* __restrict__ qy_zero, double* __restrict__ bin_obj,
+                                                      cd* __restrict__ gy_out, double* __restrict__ bin_obj,
                                                       int n2, int r, int n3, int nchunk, int jb, double eta,
                                                       double rho1, int force_eigen, int init) {
   extern __shared__ __align__(16) unsigned char sm[];
@@ -155,6 +244,50 @@ __global__ void __launch_bounds__(YS_THREADS) k_ystep(float2* __restrict__ yt, c
   float2* ynew = (float2*)(sm + L.ynew);
   const int b = blockIdx.x, tid = threadIdx.x, rr = r * r, nt = YS_THREADS;
   const bool real_bin = bin_is_real(b, n3);
+  const int ld = jb | 1;
+
+  // One batch of column-block elements per thread (four in flight): the old Y~ entries and
+  // the sums of the X~^* W~ chunk partials (fixed order).
+  float2 y[4];
+  cd acc[4];
+  auto load_batch = [&](int j0, int nj, int e0) {
+    const int nel = r * nj;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + tid + u * nt;
+      y[u] = make_float2(0.f, 0.f);
+      acc[u] = cd_make(0.0, 0.0);
+      if (e < nel) {
+        const int t = e / nj, jj = e % nj;
+        y[u] = yt[((size_t)b * r + t) * n2 + j0 + jj];
+        if (!init) {
+          const float2* bp = bpart + ((size_t)b * nchunk * r + t) * n2 + j0 + jj;
+#pragma unroll 8
+          for (int c = 0; c < nchunk; ++c) {
+            const float2 v = bp[(size_t)c * r * n2];
+            acc[u].re += v.x;
+            acc[u].im += v.y;
+          }
+        }
+      }
+    }
+  };
+  auto store_batch = [&](int nj, int e0) {
+    const int nel = r * nj;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + tid + u * nt;
+      if (e < nel) {
+        const int t = e / nj, jj = e % nj;
+        yold[t * ld + jj] = y[u];
+        bsum[t * ld + jj] = acc[u];
+      }
+    }
+  };
+  // when the first column block is one batch, its loads are issued before the G_X work
+  const int nj0 = min(jb, n2);
+  const bool early = r * nj0 <= 4 * nt;
+  if (early) load_batch(0, nj0, 0);
 
   // G_X = S + rho1 D from the chunk partials (fixed order)
   for (int e = tid; e < rr; e += nt) {
@@ -185,40 +318,11 @@ __global__ void __launch_bounds__(YS_THREADS) k_ystep(float2* __restrict__ yt, c
     }
   }
   const int np = rr < nt ? nt / rr : 1;   // partial sums per Gram entry
-  const int ld = jb | 1;
   for (int j0 = 0; j0 < n2; j0 += jb) {
     const int nj = min(jb, n2 - j0), nel = r * nj;
-    for (int e0 = 0; e0 < nel; e0 += 4 * nt) {   // four elements per thread in flight
-      float2 y[4];
-      cd acc[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + tid + u * nt;
-        y[u] = make_float2(0.f, 0.f);
-        acc[u] = cd_make(0.0, 0.0);
-        if (e < nel) {
-          const int t = e / nj, jj = e % nj;
-          y[u] = yt[((size_t)b * r + t) * n2 + j0 + jj];
-          if (!init) {
-            const float2* bp = bpart + ((size_t)b * nchunk * r + t) * n2 + j0 + jj;
-#pragma unroll 8
-            for (int c = 0; c < nchunk; ++c) {
-              const float2 v = bp[(size_t)c * r * n2];
-              acc[u].re += v.x;
-              acc[u].im += v.y;
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + tid + u * nt;
-        if (e < nel) {
-          const int t = e / nj, jj = e % nj;
-          yold[t * ld + jj] = y[u];
-          bsum[t * ld + jj] = acc[u];
-        }
-      }
+    for (int e0 = 0; e0 < nel; e0 += 4 * nt) {
+      if (!(early && j0 == 0)) load_batch(j0, nj, e0);
+      store_batch(nj, e0);
     }
     __syncthreads();
     if (!init) {
@@ -263,10 +367,34 @@ __global__ void __launch_bounds__(YS_THREADS) k_ystep(float2* __restrict__ yt, c
     __syncthreads();
   }
 
-  // the pseudo-inverse of G_Y and q = I - eta G_Y G_Y^+ for the next X-update
+  // G_Y for k_pinvy, and c_b tr(D G_Y): the rho1 term of eq. (fun-XYW) for this frequency
+  double tr = 0.0;
+  for (int e = tid; e < rr; e += nt) {
+    const int s = e / r, t = e % r;
+    gy_out[(size_t)b * rr + e] = gy[e];
+    const cd d = dm[s * r + t], g = gy[t * r + s];
+    tr += d.re * g.re - d.im * g.im;
+  }
+  tr = block_sum_d(tr, ps.red);
+  if (tid == 0) bin_obj[b] = bin_weight(b, n3) * tr;
+}
+
+// Per frequency: G_Y^+ and, unless it is exactly 0, q = I - eta G_Y G_Y^+ for the next
+// X-update (first line of eq. (updataXYW1)); qy_zero[b] = 1 marks q = 0.
+__global__ void __launch_bounds__(256) k_pinvy(const cd* __restrict__ gy_in, cd* __restrict__ gyp_out,
+                                               cd* __restrict__ qy_out, int* __restrict__ qy_zero, int r,
+                                               double eta, int force_eigen) {
+  __shared__ cd gy[TCTF_RMAX * TCTF_RMAX], gp[TCTF_RMAX * TCTF_RMAX];
+  __shared__ cd work[TCTF_RMAX * TCTF_RMAX], vec[TCTF_RMAX * TCTF_RMAX];
+  __shared__ cd colk[TCTF_RMAX], rowk[TCTF_RMAX];
+  __shared__ double rot[96], red[48];
+  PinvScratch ps{work, vec, colk, rowk, rot, red};
+  const int b = blockIdx.x, tid = threadIdx.x, rr = r * r;
+  for (int e = tid; e < rr; e += 256) gy[e] = gy_in[(size_t)b * rr + e];
+  __syncthreads();
   const int fully = pinv_herm(gy, gp, r, force_eigen, ps);
   const bool qyz = fully && eta == 1.0;
-  for (int e = tid; e < rr; e += nt) {
+  for (int e = tid; e < rr; e += 256) {
     cd qv = cd_make(0.0, 0.0);
     if (!qyz) {
       const int s = e / r, t = e % r;
@@ -277,18 +405,11 @@ __global__ void __launch_bounds__(YS_THREADS) k_ystep(float2* __restrict__ yt, c
     qy_out[(size_t)b * rr + e] = qv;
     gyp_out[(size_t)b * rr + e] = gp[e];
   }
-  // c_b tr(D G_Y): the rho1 term of eq. (fun-XYW) for this frequency
-  double tr = 0.0;
-  for (int e = tid; e < rr; e += nt) {
-    const int s = e / r, t = e % r;
-    const cd d = dm[s * r + t], g = gy[t * r + s];
-    tr += d.re * g.re - d.im * g.im;
-  }
-  tr = block_sum_d(tr, ps.red);
-  if (tid == 0) {
-    qy_zero[b] = qyz ? 1 : 0;
-    bin_obj[b] = bin_weight(b, n3) * tr;
-  }
+  if (tid == 0) qy_zero[b] = qyz ? 1 : 0;
+}
+
+void launch_pinvy(const Plan& p, hipStream_t stream) {
+  k_pinvy<<<p.nb, 256, 0, stream>>>(p.gym, p.gyp, p.qy, p.qy_zero, p.r, p.eta, p.force_eigen);
 }
 
 size_t ystep_lds_bytes(int r, int n2) { return ystep_layout(r, ystep_jb(r, n2)).total; }
@@ -301,9 +422,8 @@ void ystep_set_attr(size_t lds) {
 void launch_ystep(const Plan& p, int init) {
   const int jb = ystep_jb(p.r, p.n2);
   const size_t lds = ystep_layout(p.r, jb).total;
-  k_ystep<<<p.nb, YS_THREADS, lds, p.stream>>>(p.yt, p.bpart, p.spart, p.dpart, p.gyp, p.qy, p.qy_zero,
-                                               p.bin_obj, p.n2, p.r, p.n3, p.nchunk, jb, p.eta, p.rho1,
-                                               p.force_eigen, init);
+  k_ystep<<<p.nb, YS_THREADS, lds, p.stream>>>(p.yt, p.bpart, p.spart, p.dpart, p.gym, p.bin_obj, p.n2, p.r,
+                                               p.n3, p.nchunk, jb, p.eta, p.rho1, p.force_eigen, init);
 }
 
 }  // namespace tctf

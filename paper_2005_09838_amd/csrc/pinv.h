@@ -61,33 +61,64 @@ __device__ inline int pinv_gj_wave16(const cd* A, cd* P, int r) {
     for (int e = lane; e < rr; e += 64) P[e] = cd_make(0.0, 0.0);
     return 3;
   }
+  // Sweeps on the 2 x 2 pivot blocks K = {k0, k0 + 1} (an odd r ends with a block that
+  // holds one padding index; sweeping it leaves the leading r x r block unchanged):
+  // A_KK -> -A_KK^-1, A_iK -> A_iK A_KK^-1, A_Kj -> A_KK^-1 A_Kj,
+  // A_ij -> A_ij - A_iK A_KK^-1 A_Kj.  Sweeping every index yields -A^-1.
   bool ok = true;
-  for (int k = 0; k < r; ++k) {
-    const int ks = k & 3, src_row = 4 * k + (lane & 3), src_col = 4 * p + (k >> 2);
-    double wr[4], wi[4];
+  const int pin = p & 1;                     // this lane's row offset within a pivot block
+  for (int k0 = 0; k0 < r; k0 += 2) {
+    const int g = k0 >> 2, sl = k0 & 3;      // column group and slot of the pivot columns
+    // pivot rows k0, k0 + 1 at this lane's columns
+    double w0r[4], w0i[4], w1r[4], w1i[4];
+    const int src0 = 4 * k0 + (lane & 3), src1 = src0 + 4;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      wr[i] = __shfl(vr[i], src_row);   // (k, q0 + i)
-      wi[i] = __shfl(vi[i], src_row);
+      w0r[i] = __shfl(vr[i], src0);
+      w0i[i] = __shfl(vi[i], src0);
+      w1r[i] = __shfl(vr[i], src1);
+      w1i[i] = __shfl(vi[i], src1);
     }
-    const double ownr = ks == 0 ? vr[0] : ks == 1 ? vr[1] : ks == 2 ? vr[2] : vr[3];
-    const double owni = ks == 0 ? vi[0] : ks == 1 ? vi[1] : ks == 2 ? vi[2] : vi[3];
-    const double cr = __shfl(ownr, src_col), ci = __shfl(owni, src_col);   // (p, k)
-    const double piv = __shfl(ownr, 4 * k + (k >> 2));                      // (k, k)
-    ok = ok && piv > 0.0;   // the same in every lane; a failed pivot rejects the result
-    const double ip = piv > 0.0 ? 1.0 / piv : 0.0;
-    const bool isrow = p == k;
-    // branch-free update: pivot -> -1/piv, pivot row -> w/piv, pivot column -> c/piv,
-    // elsewhere v - c w / piv
+    // pivot columns k0, k0 + 1 of this lane's row (both in lane 4 p + g, slots sl, sl + 1)
+    const double o0r = sl == 0 ? vr[0] : vr[2], o0i = sl == 0 ? vi[0] : vi[2];
+    const double o1r = sl == 0 ? vr[1] : vr[3], o1i = sl == 0 ? vi[1] : vi[3];
+    const int srcc = 4 * p + g;
+    const double c0r = __shfl(o0r, srcc), c0i = __shfl(o0i, srcc);
+    const double c1r = __shfl(o1r, srcc), c1i = __shfl(o1i, srcc);
+    // the pivot block [[pa, pb], [conj(pb), pd]] from rows k0 and k0 + 1
+    const int sp0 = 4 * k0 + g, sp1 = sp0 + 4;
+    const double pa = __shfl(o0r, sp0), pbr = __shfl(o1r, sp0), pbi = __shfl(o1i, sp0);
+    const double pd = __shfl(o1r, sp1);
+    const double det = pa * pd - (pbr * pbr + pbi * pbi);
+    ok = ok && pa > 0.0 && det > 0.0;        // the same in every lane
+    const double idet = det > 0.0 ? 1.0 / det : 0.0;
+    // A_KK^-1 = [[e00, e01], [e10, e11]]
+    const double e00 = pd * idet, e11 = pa * idet;
+    const double e01r = -pbr * idet, e01i = -pbi * idet;   // -pb / det
+    const double e10r = -pbr * idet, e10i = pbi * idet;    // -conj(pb) / det
+    // (R0, R1) = A_pK A_KK^-1 for this lane's row
+    const double r0r = c0r * e00 + (c1r * e10r - c1i * e10i), r0i = c0i * e00 + (c1r * e10i + c1i * e10r);
+    const double r1r = (c0r * e01r - c0i * e01i) + c1r * e11, r1i = (c0r * e01i + c0i * e01r) + c1i * e11;
+    const bool inrow = (p >> 1) == (k0 >> 1);   // p is k0 or k0 + 1
+    // this lane's pivot-block row of A_KK^-1: (f0, f1) = row (p - k0)
+    const double f0r = pin ? e10r : e00, f0i = pin ? e10i : 0.0;
+    const double f1r = pin ? e11 : e01r, f1i = pin ? 0.0 : e01i;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const bool iscol = q0 + i == k;
-      const double gr = vr[i] - (cr * wr[i] - ci * wi[i]) * ip;
-      const double gi = vi[i] - (cr * wi[i] + ci * wr[i]) * ip;
-      const double nr = isrow ? (iscol ? -ip : wr[i] * ip) : (iscol ? cr * ip : gr);
-      const double ni = isrow ? (iscol ? 0.0 : wi[i] * ip) : (iscol ? ci * ip : gi);
-      vr[i] = nr;
-      vi[i] = ni;
+      const int q = q0 + i;
+      const bool incol = (q >> 1) == (k0 >> 1);
+      const int qin = q & 1;
+      // general entry: v - R0 w0 - R1 w1
+      const double gr = vr[i] - (r0r * w0r[i] - r0i * w0i[i]) - (r1r * w1r[i] - r1i * w1i[i]);
+      const double gi = vi[i] - (r0r * w0i[i] + r0i * w0r[i]) - (r1r * w1i[i] + r1i * w1r[i]);
+      // pivot rows: f0 w0 + f1 w1
+      const double hr = (f0r * w0r[i] - f0i * w0i[i]) + (f1r * w1r[i] - f1i * w1i[i]);
+      const double hi = (f0r * w0i[i] + f0i * w0r[i]) + (f1r * w1i[i] + f1i * w1r[i]);
+      // pivot columns: R_qin; pivot block: -(A_KK^-1)_(p - k0, q - k0) = -f_qin
+      const double cr = qin ? r1r : r0r, ci = qin ? r1i : r0i;
+      const double br = qin ? -f1r : -f0r, bi = qin ? -f1i : -f0i;
+      vr[i] = inrow ? (incol ? br : hr) : (incol ? cr : gr);
+      vi[i] = inrow ? (incol ? bi : hi) : (incol ? ci : gi);
     }
   }
   if (!ok) return 0;

@@ -41,6 +41,8 @@ def test_smallest_workload_50_iterations():
     (12, 1, 6, 1, 0.5),       # n2 = 1: K is empty
     (40, 65, 28, 6, 0.25),    # tube of 28 days, n2 just above a 64-column tile
     (130, 20, 16, 8, 0.6),    # several 64-row chunks in the n1 reduction
+    (48, 40, 6, 20, 0.7),     # r > 16: the largest rank bucket of the products and pivots
+    (1100, 9, 4, 2, 0.5),     # n1 > 1024: the column-in-LDS H solve
 ])
 def test_ragged_shapes(n1, n2, n3, r, p):
     d = make_inputs(n1, n2, n3, r, p=p, seed=n1 + n2 + n3, weekly=True, sigma_od=1.0, noise=0.02)
