@@ -19,6 +19,9 @@ roofline of the dominant kernel, the FP64 CPU oracle baseline, per-precision det
 
   --copy-calibration MIB   instead: run a plain device copy of MIB MiB five times (the
                            reference kernel that scales the FETCH_SIZE / WRITE_SIZE counters)
+  --batch COUNT            instead: COUNT uneven completions (synth.batch_specs) run for
+                           --steps iterations one after another and then as one batch
+                           (tctf_batch_*), printing one JSON line with both aggregate rates
 """
 from __future__ import annotations
 
@@ -119,6 +122,60 @@ def measured_traffic(stage, prec):
         return None
 
 
+def batch_bench(count, steps, warmup):
+    """Aggregate iterations/s of `count` uneven completions: sequential single-completion
+    runs (each with its own graph replays) against one batch (one graph launch per block of
+    iterations, members as independent branches)."""
+    import numpy as np
+    import torch
+    from paper_2005_09838_amd import Batch, Completion
+    from synth import batch_specs, make_inputs
+    specs = batch_specs(count)
+    dev = torch.device("cuda:0")
+    probs, nbytes = [], 0
+    for w in specs:
+        d = make_inputs(w.n1, w.n2, w.n3, w.r, sigma_od=w.sigma_od, weekly=w.weekly, noise=w.noise, p=w.p,
+                        seed=w.seed)
+        probs.append({"G": torch.from_numpy(d["G"]).to(dev), "omega": torch.from_numpy(d["omega"]).to(dev),
+                      "r": w.r, "X0": torch.from_numpy(d["X0"]).to(dev), "Y0": torch.from_numpy(d["Y0"]).to(dev)})
+        nbytes += algorithmic_bytes(w.n1, w.n2, w.n3, w.r, False)
+    singles = [Completion(pr["G"], pr["omega"], pr["r"], X0=pr["X0"], Y0=pr["Y0"]) for pr in probs]
+    for c in singles:
+        c.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in singles:
+        c.step(steps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    w_single = [c.result()["W"] for c in singles]
+    for c in singles:
+        c.close()
+    b = Batch(probs)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(bool(torch.equal(b[k].result()["W"], w_single[k])) for k in range(count))
+    b.close()
+    line = {
+        "metric": f"aggregate completion iters/s of {count} uneven completions (one batch vs one after another)",
+        "value": round(count * steps / t_batch, 2), "unit": "iters/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(1000.0 * t_batch / steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch{count}_seed1", "completions": count,
+                   "entries_total": int(sum(w.n1 * w.n2 * w.n3 for w in specs))},
+        "sequential_iters_per_s": round(count * steps / t_seq, 2),
+        "speedup_vs_sequential": round(t_seq / t_batch, 3),
+        "hbm_gbps_algorithmic_batch": round(nbytes * steps / t_batch / 1e9, 1),
+        "hbm_gbps_algorithmic_sequential": round(nbytes * steps / t_seq / 1e9, 1),
+        "batch_results_equal_single_runs": same,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def copy_calibration(mib):
     """A plain elementwise device copy of `mib` MiB (read once, written once), five times."""
     import torch
@@ -177,6 +234,7 @@ def main():
     ap.add_argument("--oracle-iters", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
+    ap.add_argument("--batch", type=int, default=0, metavar="COUNT")
     ap.add_argument("--only", choices=("fp32", "mixed"), default=None,
                     help="run one precision (no equal-error comparison); for counter runs")
     args = ap.parse_args()
@@ -186,6 +244,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.batch:
+        batch_bench(args.batch, args.steps, args.warmup)
         return
 
     import numpy as np

@@ -167,6 +167,28 @@ tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* me
 tctf_status tctf_profile(tctf_ctx* c, uint32_t mask);
 tctf_status tctf_profile_read(tctf_ctx* c, double total_us[7], int64_t launches[7]);
 
+/* ---- Batches of independent completions (one level above the per-frequency and per-row
+ * separability of one completion, section 3.2).  A batch owns n contexts of possibly
+ * different sizes, ranks and parameters, carved from one caller-owned workspace in member
+ * order (each member's part 256-byte aligned).  Pointer arguments are HOST arrays of n
+ * DEVICE pointers (X0, Y0 and seeds may be NULL, or hold NULL entries, as in tctf_create).
+ * tctf_batch_step enqueues `iters` iterations of every member: blocks of 10 iterations of
+ * all members run as ONE graph launch in which each member's chain is an independent
+ * branch (members are spread over 16 branches), then each member's remaining iterations
+ * run as tctf_step would.  Results are the same as running every member alone.
+ * tctf_batch_member gives member k's context for the per-completion calls (objective,
+ * termination, results, checkpoints); it stays owned by the batch. */
+typedef struct tctf_batch tctf_batch;
+tctf_status tctf_batch_workspace_bytes(int32_t n, const tctf_params* p, size_t* bytes);
+tctf_status tctf_batch_create(int32_t n, const tctf_params* p, const float* const* G,
+                              const uint8_t* const* omega, const float* const* X0,
+                              const float* const* Y0, const uint64_t* seeds, void* workspace,
+                              size_t ws_bytes, void* hip_stream, tctf_batch** out);
+tctf_status tctf_batch_step(tctf_batch* b, int32_t iters);
+tctf_status tctf_batch_size(tctf_batch* b, int32_t* n);
+tctf_status tctf_batch_member(tctf_batch* b, int32_t k, tctf_ctx** member);
+void tctf_batch_destroy(tctf_batch* b);   /* destroys the members too; NULL is a no-op */
+
 const char* tctf_status_string(tctf_status s);
 const char* tctf_last_error(void);  /* thread-local detail of the last failure */
 

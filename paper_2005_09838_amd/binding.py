@@ -62,6 +62,12 @@ def library() -> ctypes.CDLL:
         "tctf_complete": (I32, [PP, P, P, P, P, U64, I32, P, S, P, P, ctypes.POINTER(D)]),
         "tctf_time_stage": (I32, [P, I32, I32, ctypes.POINTER(D)]),
         "tctf_profile": (I32, [P, ctypes.c_uint32]),
+        "tctf_batch_workspace_bytes": (I32, [I32, PP, ctypes.POINTER(S)]),
+        "tctf_batch_create": (I32, [I32, PP, P, P, P, P, P, P, S, P, ctypes.POINTER(P)]),
+        "tctf_batch_step": (I32, [P, I32]),
+        "tctf_batch_size": (I32, [P, ctypes.POINTER(I32)]),
+        "tctf_batch_member": (I32, [P, I32, ctypes.POINTER(P)]),
+        "tctf_batch_destroy": (None, [P]),
         "tctf_profile_read": (I32, [P, ctypes.POINTER(D), ctypes.POINTER(I64)]),
         "tctf_status_string": (ctypes.c_char_p, [I32]),
         "tctf_last_error": (ctypes.c_char_p, []),
@@ -225,9 +231,24 @@ def _stream_handle(stream):
 class Completion:
     """One completion on the current GPU: owns the workspace tensor and the C context."""
 
+    @classmethod
+    def _member(cls, ctx, G, r, params):
+        """A view of a batch member's context (owned by the batch, not closed here)."""
+        import torch
+        self = cls.__new__(cls)
+        self.torch = torch
+        self.G = G
+        self.shape = tuple(G.shape)
+        self.r = r
+        self.params = params
+        self.ctx = ctx
+        self._owned = False
+        return self
+
     def __init__(self, G, omega, r, *, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision="fp32",
                  pinv_mode=0, eps=1e-6, X0=None, Y0=None, seed=0, stream=None):
         import torch
+        self._owned = True
         if not (G.is_cuda and omega.is_cuda):
             raise ValueError("G and omega must be device tensors")
         n1, n2, n3 = G.shape
@@ -249,9 +270,9 @@ class Completion:
                                _stream_handle(stream))
 
     def close(self):
-        if getattr(self, "ctx", None):
+        if getattr(self, "ctx", None) and getattr(self, "_owned", True):
             tctf_destroy(self.ctx)
-            self.ctx = None
+        self.ctx = None
 
     def __del__(self):
         try:
@@ -316,6 +337,77 @@ class Completion:
         names = {v: k for k, v in STAGES.items()}
         return {names[k]: (tot / cnt if cnt else None, cnt)
                 for k, (tot, cnt) in enumerate(tctf_profile_read(self.ctx))}
+
+
+class Batch:
+    """Independent completions of possibly different sizes run together (tctf_batch_*).
+
+    problems: list of dicts with keys G, omega (device tensors), r and optionally mu, rho1,
+    rho2, eta, precision, X0, Y0, seed."""
+
+    def __init__(self, problems, stream=None):
+        import torch
+        n = len(problems)
+        self.torch = torch
+        self.params = (tctf_params * n)()
+        keep = []
+        ptrs = {k: (ctypes.c_void_p * n)() for k in ("G", "omega", "X0", "Y0")}
+        seeds = (ctypes.c_uint64 * n)()
+        self.shapes = []
+        for k, pr in enumerate(problems):
+            G = pr["G"].contiguous().to(torch.float32)
+            om = pr["omega"].contiguous().to(torch.uint8)
+            n1, n2, n3 = G.shape
+            self.params[k] = make_params(n1, n2, n3, pr["r"], pr.get("mu", 1e-2), pr.get("rho1", 1e-2),
+                                         pr.get("rho2", 1e-2), pr.get("eta", 1.0), pr.get("precision", "fp32"))
+            ptrs["G"][k], ptrs["omega"][k] = G.data_ptr(), om.data_ptr()
+            keep += [G, om]
+            for key in ("X0", "Y0"):
+                if pr.get(key) is not None:
+                    t = pr[key].contiguous().to(torch.float32)
+                    keep.append(t)
+                    ptrs[key][k] = t.data_ptr()
+            seeds[k] = pr.get("seed", 0)
+            self.shapes.append((G, pr["r"]))
+        nbytes = ctypes.c_size_t()
+        _check(library().tctf_batch_workspace_bytes(n, self.params, ctypes.byref(nbytes)),
+               "tctf_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=problems[0]["G"].device)
+        ws = (self.workspace.data_ptr() + 255) & ~255
+        out = ctypes.c_void_p()
+        _check(library().tctf_batch_create(n, self.params, ptrs["G"], ptrs["omega"], ptrs["X0"], ptrs["Y0"], seeds,
+                                           ws, nbytes.value, _stream_handle(stream), ctypes.byref(out)),
+               "tctf_batch_create")
+        self.batch = out.value
+        self.members = []
+        for k in range(n):
+            m = ctypes.c_void_p()
+            _check(library().tctf_batch_member(self.batch, k, ctypes.byref(m)), "tctf_batch_member")
+            G, r = self.shapes[k]
+            self.members.append(Completion._member(m.value, G, r, self.params[k]))
+
+    def step(self, iters=1):
+        _check(library().tctf_batch_step(self.batch, iters), "tctf_batch_step")
+        return self
+
+    def __len__(self):
+        return len(self.members)
+
+    def __getitem__(self, k):
+        return self.members[k]
+
+    def close(self):
+        if getattr(self, "batch", None):
+            for m in self.members:
+                m.ctx = None
+            library().tctf_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def complete(M, omega, r, lam=1e-2, rho1=1e-2, rho2=1e-2, iters=50, precision="fp32", X0=None, Y0=None,

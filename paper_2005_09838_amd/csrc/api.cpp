@@ -611,3 +611,168 @@ const char* tctf_status_string(tctf_status s) {
 const char* tctf_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batches of completions
+// Independent completions (the frequencies and rows of one completion are already
+// independent work units; several completions are one level up).  Blocks of GRAPH_ITERS
+// iterations of every member are captured once into a single graph in which each member's
+// chain is its own branch, so one launch runs all members and the runtime may overlap them.
+struct tctf_batch {
+  std::vector<tctf_ctx*> members;
+  std::vector<hipStream_t> streams;   // capture streams, one branch each
+  hipStream_t origin = nullptr;       // capture origin
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> done_ev;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t stream = nullptr;       // the caller's stream
+};
+
+#define BATCH_BRANCHES 16
+
+extern "C" {
+
+tctf_status tctf_batch_workspace_bytes(int32_t n, const tctf_params* p, size_t* bytes) {
+  if (n < 1 || !p || !bytes) return fail(TCTF_E_ARG, "n must be >= 1 and pointers non-NULL");
+  size_t total = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    size_t b = 0;
+    tctf_status s = tctf_workspace_bytes(&p[k], &b);
+    if (s != TCTF_OK) return s;
+    total += align256(b);
+  }
+  *bytes = total;
+  return TCTF_OK;
+}
+
+void tctf_batch_destroy(tctf_batch* b) {
+  if (!b) return;
+  if (b->graph_exec) {
+    (void)hipStreamSynchronize(b->stream);
+    hipGraphExecDestroy(b->graph_exec);
+  }
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->done_ev) hipEventDestroy(e);
+  if (b->fork_ev) hipEventDestroy(b->fork_ev);
+  for (hipStream_t s : b->streams) hipStreamDestroy(s);
+  if (b->origin) hipStreamDestroy(b->origin);
+  for (tctf_ctx* c : b->members) tctf_destroy(c);
+  delete b;
+}
+
+tctf_status tctf_batch_create(int32_t n, const tctf_params* p, const float* const* G, const uint8_t* const* omega,
+                              const float* const* X0, const float* const* Y0, const uint64_t* seeds,
+                              void* workspace, size_t ws_bytes, void* hip_stream, tctf_batch** out) {
+  if (!out) return fail(TCTF_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || !p || !G || !omega) return fail(TCTF_E_ARG, "n must be >= 1; p, G and omega non-NULL");
+  size_t need = 0;
+  tctf_status s = tctf_batch_workspace_bytes(n, p, &need);
+  if (s != TCTF_OK) return s;
+  if (!workspace) return fail(TCTF_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace & 255u) != 0) return fail(TCTF_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < need) return fail(TCTF_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+  tctf_batch* b = new (std::nothrow) tctf_batch();
+  if (!b) return fail(TCTF_E_ARG, "out of host memory");
+  b->stream = (hipStream_t)hip_stream;
+  unsigned char* w = (unsigned char*)workspace;
+  for (int32_t k = 0; k < n; ++k) {
+    size_t bytes = 0;
+    (void)tctf_workspace_bytes(&p[k], &bytes);
+    tctf_ctx* c = nullptr;
+    s = tctf_create(&p[k], G[k], omega[k], X0 ? X0[k] : nullptr, Y0 ? Y0[k] : nullptr, seeds ? seeds[k] : 0, w,
+                    align256(bytes), hip_stream, &c);
+    if (s != TCTF_OK) {
+      const std::string why = g_err;
+      tctf_batch_destroy(b);
+      return fail(s, "member %d: %s", k, why.c_str());
+    }
+    b->members.push_back(c);
+    w += align256(bytes);
+  }
+  *out = b;
+  return TCTF_OK;
+}
+
+static tctf_status batch_graph(tctf_batch* b) {
+  if (b->graph_exec) return TCTF_OK;
+  const int nbr = (int)b->members.size() < BATCH_BRANCHES ? (int)b->members.size() : BATCH_BRANCHES;
+  if (!b->origin) HIP_TRY(hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking));
+  if (!b->fork_ev) HIP_TRY(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+  while ((int)b->streams.size() < nbr) {
+    hipStream_t st;
+    hipEvent_t ev;
+    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    b->streams.push_back(st);
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    b->done_ev.push_back(ev);
+  }
+  HIP_TRY(hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipEventRecord(b->fork_ev, b->origin);
+  tctf_status s = TCTF_OK;
+  for (int q = 0; q < nbr && e == hipSuccess && s == TCTF_OK; ++q) {
+    e = hipStreamWaitEvent(b->streams[q], b->fork_ev, 0);
+    for (int it = 0; it < GRAPH_ITERS && e == hipSuccess && s == TCTF_OK; ++it) {
+      for (size_t k = q; k < b->members.size() && s == TCTF_OK; k += nbr) {
+        tctf_ctx* c = b->members[k];
+        const hipStream_t user = c->plan.stream;
+        c->plan.stream = b->streams[q];
+        s = enqueue_iteration(c);
+        c->plan.stream = user;
+      }
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->done_ev[q], b->streams[q]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->origin, b->done_ev[q], 0);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->origin, &g);
+  if (s != TCTF_OK) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) {
+    b->graph = g;
+    e = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
+  }
+  if (e != hipSuccess) {
+    b->graph_exec = nullptr;
+    return fail(TCTF_E_HIP, "graph capture of the batch: %s", hipGetErrorString(e));
+  }
+  return TCTF_OK;
+}
+
+tctf_status tctf_batch_step(tctf_batch* b, int32_t iters) {
+  if (!b) return fail(TCTF_E_ARG, "batch is NULL");
+  if (iters < 0) return fail(TCTF_E_ARG, "iters must be >= 0");
+  int32_t it = 0;
+  if (iters - 1 >= GRAPH_ITERS) {
+    tctf_status s = batch_graph(b);
+    if (s != TCTF_OK) return s;
+    for (; iters - 1 - it >= GRAPH_ITERS; it += GRAPH_ITERS) {
+      HIP_TRY(hipGraphLaunch(b->graph_exec, b->stream));
+      for (tctf_ctx* c : b->members) c->iters += GRAPH_ITERS;
+    }
+  }
+  // the remainder (always including the last iteration and its termination snapshot)
+  for (tctf_ctx* c : b->members) {
+    tctf_status s = tctf_step(c, iters - it);
+    if (s != TCTF_OK) return s;
+  }
+  return TCTF_OK;
+}
+
+tctf_status tctf_batch_size(tctf_batch* b, int32_t* n) {
+  if (!b || !n) return fail(TCTF_E_ARG, "NULL argument");
+  *n = (int32_t)b->members.size();
+  return TCTF_OK;
+}
+
+tctf_status tctf_batch_member(tctf_batch* b, int32_t k, tctf_ctx** member) {
+  if (!b || !member) return fail(TCTF_E_ARG, "NULL argument");
+  if (k < 0 || k >= (int32_t)b->members.size()) return fail(TCTF_E_ARG, "member %d out of range", k);
+  *member = b->members[k];
+  return TCTF_OK;
+}
+
+}  // extern "C"

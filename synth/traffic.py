@@ -137,3 +137,22 @@ def make_workload(name_or_workload, **overrides) -> tuple[Workload, dict]:
     data = make_inputs(w.n1, w.n2, w.n3, w.r, sigma_od=w.sigma_od, weekly=w.weekly,
                        noise=w.noise, p=w.p, seed=w.seed, holdout=w.holdout)
     return w, data
+
+
+def batch_specs(count: int = 64, seed: int = 1) -> list[Workload]:
+    """Sizes of a batch of uneven completions: for each completion, in this order,
+    n1 from {36, 144, 529}, n2 from {48, 96, 288}, n3 from {7, 28, 112}, r uniform in
+    [2, 16] and p uniform in [0.2, 0.6), all drawn from ``default_rng(seed)``; data seed
+    1000 + t, log-normal(0, 1) OD scales, diurnal and weekly profiles, 2 % noise, 50
+    iterations."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(count):
+        n1 = int(rng.choice([36, 144, 529]))
+        n2 = int(rng.choice([48, 96, 288]))
+        n3 = int(rng.choice([7, 28, 112]))
+        r = int(rng.integers(2, 17))
+        p = float(rng.uniform(0.2, 0.6))
+        out.append(Workload(f"batch{t}_{n1}x{n2}x{n3}_r{r}", n1, n2, n3, r, 1.0, True, 0.02, p, 50,
+                            seed=1000 + t))
+    return out

@@ -127,3 +127,43 @@ def test_graph_replays_match_eager_launches():
         assert np.array_equal(wg, we), k
         assert cg.objective() == ce.objective()
     ce.profile([])
+
+
+def test_batch_members_match_single_runs():
+    """Uneven completions run as one batch give, bit for bit, what each gives alone."""
+    import torch
+    from paper_2005_09838_amd import Batch
+    shapes = [(36, 48, 7, 3, 0.3), (20, 30, 12, 4, 0.5), (64, 24, 28, 6, 0.4), (9, 40, 5, 2, 0.6),
+              (50, 17, 16, 5, 0.35), (33, 33, 9, 3, 0.45), (12, 12, 4, 1, 0.5)]
+    probs, data = [], []
+    for k, (n1, n2, n3, r, p) in enumerate(shapes):
+        d = make_inputs(n1, n2, n3, r, p=p, seed=40 + k, weekly=True)
+        data.append((d, r))
+        probs.append({"G": to_dev(d["G"]), "omega": to_dev(d["omega"]), "r": r, "X0": to_dev(d["X0"]),
+                      "Y0": to_dev(d["Y0"]), "mu": 0.02 * (k + 1), "rho1": 0.01, "rho2": 0.03})
+    b = Batch(probs)
+    assert len(b) == len(shapes)
+    b.step(23)
+    for k, (d, r) in enumerate(data):
+        a = gpu_run(d, r, 23, mu=0.02 * (k + 1), rho1=0.01, rho2=0.03)
+        wb = b[k].result()["W"].cpu().numpy()
+        assert np.array_equal(wb, a["W"].astype(np.float32)), k
+        assert b[k].objective() == a["f0"][-1], k
+        assert b[k].iterations == 23
+    b.close()
+    del torch
+
+
+def test_batch_member_against_oracle():
+    from paper_2005_09838_amd import Batch
+    d = make_inputs(30, 26, 10, 3, p=0.4, seed=77)
+    d2 = make_inputs(18, 40, 6, 2, p=0.5, seed=78)
+    b = Batch([{"G": to_dev(d["G"]), "omega": to_dev(d["omega"]), "r": 3, "X0": to_dev(d["X0"]), "Y0": to_dev(d["Y0"])},
+               {"G": to_dev(d2["G"]), "omega": to_dev(d2["omega"]), "r": 2, "X0": to_dev(d2["X0"]),
+                "Y0": to_dev(d2["Y0"])}])
+    b.step(12)
+    st, info = oracle_run(d, 3, 12)
+    assert rel(b[0].result()["W"].cpu().numpy(), st.w) < 1e-5
+    st2, _ = oracle_run(d2, 2, 12)
+    assert rel(b[1].result()["W"].cpu().numpy(), st2.w) < 1e-5
+    b.close()
