@@ -86,7 +86,7 @@ def run_precision(prec, d, w, steps, warmup, dev, torch):
     c.step(warmup)
     c.profile(STAGE_NAMES)
     c.step(20)
-    stages = {name: us for name, (us, n) in c.profile_read().items()}
+    stages = {name: us for name, (us, n) in c.profile_read().items() if n}
     dominant = max(stages, key=stages.get)
     c.profile([])
     torch.cuda.synchronize()

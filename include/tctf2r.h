@@ -118,6 +118,13 @@ tctf_status tctf_objective(tctf_ctx* c, double* f0);
  * out[3] = 1 if all three are <= eps.  Needs at least one iteration since create. */
 tctf_status tctf_termination(tctf_ctx* c, double out[4]);
 
+/* Iterate until the step-6 test of the algorithm box holds or max_iters iterations have
+ * run: blocks of check_every iterations (tctf_step), each followed by tctf_termination on
+ * the block's last iteration.  *iters_run = iterations run by this call; *converged = 1 if
+ * the test held (then it held on iteration *iters_run).  Synchronises after every block. */
+tctf_status tctf_run(tctf_ctx* c, int32_t max_iters, int32_t check_every, int32_t* iters_run,
+                     int32_t* converged);
+
 /* Synchronise and return stationarity measures at the current iterate (Theorem ThKKT,
  * eq. (AKKTstar)): out[0] = sqrt(sum_k ||grad_X h_k||^2 + ||grad_Y h_k||^2) /
  * (||W~|| (||X~|| + ||Y~||)) over the full spectrum; out[1] = max over unobserved entries

@@ -62,6 +62,7 @@ def library() -> ctypes.CDLL:
         "tctf_complete": (I32, [PP, P, P, P, P, U64, I32, P, S, P, P, ctypes.POINTER(D)]),
         "tctf_time_stage": (I32, [P, I32, I32, ctypes.POINTER(D)]),
         "tctf_profile": (I32, [P, ctypes.c_uint32]),
+        "tctf_run": (I32, [P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "tctf_batch_workspace_bytes": (I32, [I32, PP, ctypes.POINTER(S)]),
         "tctf_batch_create": (I32, [I32, PP, P, P, P, P, P, P, S, P, ctypes.POINTER(P)]),
         "tctf_batch_step": (I32, [P, I32]),
@@ -283,6 +284,13 @@ class Completion:
     def step(self, iters=1):
         tctf_step(self.ctx, iters)
         return self
+
+    def run(self, max_iters, check_every=10):
+        """Iterate until the step-6 termination test holds; returns (iterations run, converged)."""
+        n, conv = ctypes.c_int32(), ctypes.c_int32()
+        _check(library().tctf_run(self.ctx, max_iters, check_every, ctypes.byref(n), ctypes.byref(conv)),
+               "tctf_run")
+        return n.value, bool(conv.value)
 
     def objective(self):
         return tctf_objective(self.ctx)

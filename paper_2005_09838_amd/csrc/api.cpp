@@ -253,8 +253,8 @@ static tctf_status enqueue_iteration(tctf_ctx* c) {
   if (s == TCTF_OK) s = stage(c, 3, [&] { tctf::launch_hsolve(p); });
   if (s == TCTF_OK) s = stage(c, 4, [&] { tctf::launch_bgemm(p); });
   if (s == TCTF_OK) s = stage(c, 5, [&] { tctf::launch_ystep(p, 0); });
-  if (s == TCTF_OK) s = stage(c, 6, [&] { tctf::launch_pinvy(p, p.stream); });
-  if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p); });
+  // Z~ = X~Y~, with G_Y^+ and I - eta P_Y for the next X-step in extra blocks of the launch
+  if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p, 1); });
   if (s == TCTF_OK) s = stage(c, 0, [&] { tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0); });
   if (s != TCTF_OK) return s;
   return check_launch();
@@ -289,6 +289,8 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   tctf::slice_set_attr(p.n3, tctf::slice_lds_bytes(p.n2, p.n3));
   tctf::ystep_set_attr(tctf::ystep_lds_bytes(p.r, p.n2));
   tctf::bgemm_set_attr(tctf::bgemm_lds_bytes(p.r, p.chunk));
+  tctf::pinvy_set_attr(p.r);
+  tctf::zgemm_set_attr(p.r);
   tctf::launch_zero(p, p.flag, 64);
   tctf::launch_zero(p, p.qy_zero, (size_t)p.nb * 4);
   tctf::launch_pack_g(p, G, omega);
@@ -408,6 +410,28 @@ tctf_status tctf_termination(tctf_ctx* c, double out[4]) {
   if (s != TCTF_OK) return s;
   const double eps = c->prm.eps;
   out[3] = (out[0] <= eps && out[1] <= eps && out[2] <= eps) ? 1.0 : 0.0;
+  return TCTF_OK;
+}
+
+tctf_status tctf_run(tctf_ctx* c, int32_t max_iters, int32_t check_every, int32_t* iters_run,
+                     int32_t* converged) {
+  if (!c || !iters_run || !converged) return fail(TCTF_E_ARG, "NULL argument");
+  if (max_iters < 0 || check_every < 1) return fail(TCTF_E_ARG, "max_iters must be >= 0 and check_every >= 1");
+  *iters_run = 0;
+  *converged = 0;
+  while (*iters_run < max_iters) {
+    const int32_t k = check_every < max_iters - *iters_run ? check_every : max_iters - *iters_run;
+    tctf_status s = tctf_step(c, k);
+    if (s != TCTF_OK) return s;
+    *iters_run += k;
+    double t[4];
+    s = tctf_termination(c, t);
+    if (s != TCTF_OK) return s;
+    if (t[3] != 0.0) {
+      *converged = 1;
+      break;
+    }
+  }
   return TCTF_OK;
 }
 

@@ -56,7 +56,7 @@ void launch_zero(const Plan& p, void* dst, size_t bytes);
 enum SliceMode { SLICE_INIT = 0, SLICE_ITER = 1, SLICE_RESULT = 2, SLICE_KKT = 3 };
 bool slice_supported(int n3);
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g);
-void launch_zgemm(const Plan& p);
+void launch_zgemm(const Plan& p, int with_pinv = 0);   // with_pinv: also G_Y^+ (pinvy_block)
 void launch_agemm(const Plan& p, int raw_a = 0);
 void launch_hsolve(const Plan& p);
 void launch_bgemm(const Plan& p);
@@ -64,6 +64,8 @@ size_t bgemm_lds_bytes(int r, int chunk);
 void bgemm_set_attr(size_t lds);
 void launch_ystep(const Plan& p, int init);
 void launch_pinvy(const Plan& p, hipStream_t stream);
+void pinvy_set_attr(int r);
+void zgemm_set_attr(int r);
 void launch_objective(const Plan& p);
 void launch_termination(const Plan& p);
 void launch_stationarity(const Plan& p, int w_from_g);

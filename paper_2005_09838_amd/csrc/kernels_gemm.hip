@@ -11,6 +11,7 @@
 // r x r Grams and the X right-hand side epilogue are FP64.  Mixed mode reads W~ from its
 // BF16 storage and converts to FP32 before the product.
 #include "kernels.h"
+#include "pinv.h"
 
 namespace tctf {
 
@@ -49,13 +50,24 @@ __device__ __forceinline__ float4 ld_wt2(const void* wt, size_t idx, int valid, 
 // Block: 64 rows x one frequency, 4 wavefronts of 16 rows; Y~ staged in LDS by column
 // chunks of ZG_COLS; each wavefront sweeps its rows across the chunk in groups of 4
 // 16-column tiles.  Output tiles go straight to the interleaved Z~ rows.
+// The first npinv blocks instead form G_Y^+ and I - eta P_Y of frequency blockIdx.x for
+// the next X-step (pinvy_block): independent work that runs beside the product.
 #define ZG_ROWS 64
 #define ZG_COLS 128
 template <int RM>   // r <= RM: every loop below has a compile-time trip count
 __global__ void __launch_bounds__(256) k_zgemm(const float2* __restrict__ xt, const float2* __restrict__ yt,
-                                               float2* __restrict__ zt, int n1, int n2, int r, int nb) {
-  __shared__ float2 ysh[TCTF_RMAX * ZG_COLS];   // [s][j] of the column chunk
-  const int i0 = blockIdx.x * ZG_ROWS, b = blockIdx.y, tid = threadIdx.x;
+                                               float2* __restrict__ zt, int n1, int n2, int r, int nb,
+                                               int npinv, const cd* __restrict__ gym, cd* __restrict__ gyp,
+                                               cd* __restrict__ qy, int* __restrict__ qy_zero, double eta,
+                                               int force_eigen) {
+  extern __shared__ __align__(16) unsigned char zsm[];
+  if ((int)blockIdx.x < npinv) {
+    pinvy_block(blockIdx.x, gym, gyp, qy, qy_zero, r, eta, force_eigen, zsm);
+    return;
+  }
+  float2* ysh = (float2*)zsm;   // [s][j] of the column chunk
+  const int bid = blockIdx.x - npinv, ntile = (n1 + ZG_ROWS - 1) / ZG_ROWS;
+  const int i0 = (bid % ntile) * ZG_ROWS, b = bid / ntile, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
   constexpr int KS = RM / 2;   // K steps of 4 over 2r <= 2 RM
   constexpr int YPER = RM * ZG_COLS / 256;
@@ -123,11 +135,25 @@ __global__ void __launch_bounds__(256) k_zgemm(const float2* __restrict__ xt, co
   }
 }
 
-void launch_zgemm(const Plan& p) {
-  dim3 grid((p.n1 + ZG_ROWS - 1) / ZG_ROWS, p.nb);
-  if (p.r <= 8) k_zgemm<8><<<grid, 256, 0, p.stream>>>(p.xt, p.yt, p.zt, p.n1, p.n2, p.r, p.nb);
-  else if (p.r <= 16) k_zgemm<16><<<grid, 256, 0, p.stream>>>(p.xt, p.yt, p.zt, p.n1, p.n2, p.r, p.nb);
-  else k_zgemm<32><<<grid, 256, 0, p.stream>>>(p.xt, p.yt, p.zt, p.n1, p.n2, p.r, p.nb);
+void zgemm_set_attr(int r) {
+  if (pinvy_lds_bytes(r) > 65536)
+    (void)hipFuncSetAttribute((const void*)k_zgemm<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)pinvy_lds_bytes(r));
+}
+
+void launch_zgemm(const Plan& p, int with_pinv) {
+  const int npinv = with_pinv ? p.nb : 0;
+  const int grid = npinv + (p.n1 + ZG_ROWS - 1) / ZG_ROWS * p.nb;
+  const int rm = p.r <= 8 ? 8 : (p.r <= 16 ? 16 : 32);
+  size_t lds = (size_t)rm * ZG_COLS * sizeof(float2);
+  if (with_pinv && pinvy_lds_bytes(p.r) > lds) lds = pinvy_lds_bytes(p.r);
+#define TCTF_ZGEMM(RM)                                                                                   \
+  k_zgemm<RM><<<grid, 256, lds, p.stream>>>(p.xt, p.yt, p.zt, p.n1, p.n2, p.r, p.nb, npinv, p.gym, p.gyp, \
+                                           p.qy, p.qy_zero, p.eta, p.force_eigen)
+  if (p.r <= 8) TCTF_ZGEMM(8);
+  else if (p.r <= 16) TCTF_ZGEMM(16);
+  else TCTF_ZGEMM(32);
+#undef TCTF_ZGEMM
 }
 
 // ---------------------------------------------------------------- A = W~ Y~^*, X right-hand side

@@ -319,9 +319,9 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
 // so each thread composes its segment's map, the S maps of a row are combined by a
 // scan across the S lanes, and each thread then runs its segment once more from the
 // right boundary value.  S divides 64 and is a power of two; L <= LMAX.
-template <int LMAX>
+template <int LMAX, int S>
 __device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* tab, const uint32_t* obits, int nwr,
-                                                int n2, int N, float rho2, int S) {
+                                                int n2, int N, float rho2) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int L = (n2 + S - 1) / S;
   for (int kk = tid; kk < N * S; kk += nt) {
@@ -482,7 +482,15 @@ __global__ void __launch_bounds__(1024) k_slice_coop(SliceArgs a) {
     int S = 1;
     while (S < 64 && 2 * S * N <= nt) S <<= 1;
     while ((n2 + S - 1) / S > 16) S <<= 1;   // segment length within the register budget
-    wstep_segmented<16>(zs, LD, tab, obits, nwr, n2, N, a.rho2, S);
+    switch (S) {   // the segment count is a compile-time constant of the shuffles
+      case 1: wstep_segmented<16, 1>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 2: wstep_segmented<16, 2>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 4: wstep_segmented<16, 4>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 8: wstep_segmented<16, 8>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 16: wstep_segmented<16, 16>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 32: wstep_segmented<16, 32>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      default: wstep_segmented<16, 64>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+    }
   }
   __syncthreads();
 

@@ -379,37 +379,23 @@ __global__ void __launch_bounds__(YS_THREADS) k_ystep(float2* __restrict__ yt, c
   if (tid == 0) bin_obj[b] = bin_weight(b, n3) * tr;
 }
 
-// Per frequency: G_Y^+ and, unless it is exactly 0, q = I - eta G_Y G_Y^+ for the next
-// X-update (first line of eq. (updataXYW1)); qy_zero[b] = 1 marks q = 0.
+// Per frequency: G_Y^+ and I - eta P_Y (pinvy_block).  In the iteration this work rides
+// along the Z~ product (k_zgemm); this kernel serves create and stage timing.
 __global__ void __launch_bounds__(256) k_pinvy(const cd* __restrict__ gy_in, cd* __restrict__ gyp_out,
                                                cd* __restrict__ qy_out, int* __restrict__ qy_zero, int r,
                                                double eta, int force_eigen) {
-  __shared__ cd gy[TCTF_RMAX * TCTF_RMAX], gp[TCTF_RMAX * TCTF_RMAX];
-  __shared__ cd work[TCTF_RMAX * TCTF_RMAX], vec[TCTF_RMAX * TCTF_RMAX];
-  __shared__ cd colk[TCTF_RMAX], rowk[TCTF_RMAX];
-  __shared__ double rot[96], red[48];
-  PinvScratch ps{work, vec, colk, rowk, rot, red};
-  const int b = blockIdx.x, tid = threadIdx.x, rr = r * r;
-  for (int e = tid; e < rr; e += 256) gy[e] = gy_in[(size_t)b * rr + e];
-  __syncthreads();
-  const int fully = pinv_herm(gy, gp, r, force_eigen, ps);
-  const bool qyz = fully && eta == 1.0;
-  for (int e = tid; e < rr; e += 256) {
-    cd qv = cd_make(0.0, 0.0);
-    if (!qyz) {
-      const int s = e / r, t = e % r;
-      cd acc = cd_make(0.0, 0.0);
-      for (int u = 0; u < r; ++u) cd_fma(acc, gy[s * r + u], gp[u * r + t]);
-      qv = cd_make((s == t ? 1.0 : 0.0) - eta * acc.re, -eta * acc.im);
-    }
-    qy_out[(size_t)b * rr + e] = qv;
-    gyp_out[(size_t)b * rr + e] = gp[e];
-  }
-  if (tid == 0) qy_zero[b] = qyz ? 1 : 0;
+  extern __shared__ __align__(16) unsigned char psm[];
+  pinvy_block(blockIdx.x, gy_in, gyp_out, qy_out, qy_zero, r, eta, force_eigen, psm);
+}
+
+void pinvy_set_attr(int r) {
+  if (pinvy_lds_bytes(r) > 65536)
+    (void)hipFuncSetAttribute((const void*)k_pinvy, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)pinvy_lds_bytes(r));
 }
 
 void launch_pinvy(const Plan& p, hipStream_t stream) {
-  k_pinvy<<<p.nb, 256, 0, stream>>>(p.gym, p.gyp, p.qy, p.qy_zero, p.r, p.eta, p.force_eigen);
+  k_pinvy<<<p.nb, 256, pinvy_lds_bytes(p.r), stream>>>(p.gym, p.gyp, p.qy, p.qy_zero, p.r, p.eta, p.force_eigen);
 }
 
 size_t ystep_lds_bytes(int r, int n2) { return ystep_layout(r, ystep_jb(r, n2)).total; }

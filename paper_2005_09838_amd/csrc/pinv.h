@@ -288,3 +288,42 @@ __device__ inline int pinv_herm(const cd* A, cd* P, int r, int force_eigen, Pinv
   __syncthreads();
   return kept == r ? 1 : 0;
 }
+
+// Bytes of LDS pinvy_block needs at rank r.
+__host__ __device__ inline size_t pinvy_lds_bytes(int r) {
+  return (size_t)(4 * r * r + 2 * r) * sizeof(cd) + 144 * sizeof(double);
+}
+
+// Per frequency b, by a whole block: G_Y^+ from the Gram G_Y in gym and, unless it is
+// exactly 0, q = I - eta G_Y G_Y^+ for the next X-update (first line of eq. (updataXYW1));
+// qy_zero[b] = 1 marks q = 0.  sm: pinvy_lds_bytes(r) bytes of LDS.
+__device__ inline void pinvy_block(int b, const cd* __restrict__ gym, cd* __restrict__ gyp, cd* __restrict__ qy,
+                                   int* __restrict__ qy_zero, int r, double eta, int force_eigen,
+                                   unsigned char* sm) {
+  const int tid = threadIdx.x, nt = blockDim.x, rr = r * r;
+  cd* gy = (cd*)sm;
+  cd* gp = gy + rr;
+  PinvScratch ps;
+  ps.work = gp + rr;
+  ps.vec = ps.work + rr;
+  ps.colk = ps.vec + rr;
+  ps.rowk = ps.colk + r;
+  ps.rot = (double*)(ps.rowk + r);
+  ps.red = ps.rot + 96;
+  for (int e = tid; e < rr; e += nt) gy[e] = gym[(size_t)b * rr + e];
+  __syncthreads();
+  const int fully = pinv_herm(gy, gp, r, force_eigen, ps);
+  const bool qyz = fully && eta == 1.0;
+  for (int e = tid; e < rr; e += nt) {
+    cd qv = cd_make(0.0, 0.0);
+    if (!qyz) {
+      const int s = e / r, t = e % r;
+      cd acc = cd_make(0.0, 0.0);
+      for (int u = 0; u < r; ++u) cd_fma(acc, gy[s * r + u], gp[u * r + t]);
+      qv = cd_make((s == t ? 1.0 : 0.0) - eta * acc.re, -eta * acc.im);
+    }
+    qy[(size_t)b * rr + e] = qv;
+    gyp[(size_t)b * rr + e] = gp[e];
+  }
+  if (tid == 0) qy_zero[b] = qyz ? 1 : 0;
+}

@@ -173,3 +173,30 @@ def test_default_initialisation():
     g = gpu_run(d, 3, 10, x0=False, y0=False, seed=123, history=True)
     f = np.array(g["f0"])
     assert np.all(np.isfinite(f)) and f[-1] < f[0]
+
+
+def test_run_until_termination_stops_where_the_oracle_does():
+    """Step 6 driving the loop: with check_every = 1 the run stops at the first iteration
+    whose termination quantities all fall below eps, the same iteration as in FP64."""
+    from tests.gpu_helpers import to_dev
+    from paper_2005_09838_amd import Completion
+    d = make_inputs(18, 14, 6, 3, p=0.6, seed=12)
+    prob = oracle.Problem(d["G"], d["omega"], 3, 1e-2, 1e-2, 1e-2)
+    st = oracle.initial_state(prob, d["X0"], d["Y0"])
+    maxima = []
+    for _ in range(40):
+        nxt = oracle.iterate(prob, st)
+        maxima.append(max(oracle.termination(st, nxt)))
+        st = nxt
+    # a stopping iteration with a clear margin (a few per cent) on both sides of eps
+    n_stop = next(n for n in range(8, 40) if maxima[n] < 0.95 * maxima[n - 1])
+    eps = (maxima[n_stop] * maxima[n_stop - 1]) ** 0.5
+    assert all(m > eps for m in maxima[:n_stop])
+    c = Completion(to_dev(d["G"]), to_dev(d["omega"]), 3, X0=to_dev(d["X0"]), Y0=to_dev(d["Y0"]), eps=eps)
+    n, conv = c.run(200, check_every=1)
+    assert conv and n == n_stop + 1, (n, n_stop + 1, eps)
+    t = c.termination()
+    assert t[3] == 1.0 and max(t[:3]) <= eps
+    c2 = Completion(to_dev(d["G"]), to_dev(d["omega"]), 3, X0=to_dev(d["X0"]), Y0=to_dev(d["Y0"]), eps=eps)
+    n2, conv2 = c2.run(n_stop, check_every=4)   # stops at the budget before the test holds
+    assert not conv2 and n2 == n_stop
