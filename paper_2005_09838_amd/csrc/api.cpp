@@ -16,9 +16,7 @@
 
 namespace tctf {
 size_t slice_lds_bytes(int n2, int n3);
-size_t ystep_lds_bytes(int r, int n2);
 void slice_set_attr(int n3, size_t lds);
-void ystep_set_attr(size_t lds);
 }  // namespace tctf
 
 using tctf::Plan;
@@ -51,7 +49,7 @@ struct StateHeader {
 };
 
 struct Layout {
-  size_t gp, wt, zt, xt, yt, rhs, bpart, spart, dpart, gym, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
+  size_t gp, wt, zt, xt, yt, rhs, bpart, gxm, dmat, gxp, qx, qx_zero, gym, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
       flag, scal, xt_prev, yt_prev, wt_prev, stat_work, kkt, total;
   size_t state_bytes;
 };
@@ -76,8 +74,9 @@ static void chunking(int n1, int nb, int* nchunk, int* chunk) {
 static Layout make_layout(const tctf_params& p) {
   Layout L;
   const size_t n1 = p.n1, n2 = p.n2, n3 = p.n3, r = p.r, nb = n3 / 2 + 1;
-  int nchunk, chunk;
+  int nchunk, chunk, ny, ycw;
   chunking(p.n1, (int)nb, &nchunk, &chunk);
+  tctf::ystep_split(p.n2, p.r, (int)nb, &ny, &ycw);
   const size_t welem = p.precision == TCTF_MIXED_BF16 ? 4 : 8;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
@@ -88,9 +87,12 @@ static Layout make_layout(const tctf_params& p) {
   L.yt = take(nb * r * n2 * 8);
   L.rhs = take(nb * r * n1 * 8);
   L.bpart = take(nb * nchunk * r * n2 * 8);
-  L.spart = take(nb * nchunk * r * r * 16);
-  L.dpart = take(nb * nchunk * r * r * 16);
-  L.gym = take(nb * r * r * 16);
+  L.gxm = take(nb * r * r * 16);
+  L.dmat = take(nb * r * r * 16);
+  L.gxp = take(nb * r * r * 16);
+  L.qx = take(nb * r * r * 16);
+  L.qx_zero = take(nb * 4);
+  L.gym = take(nb * ny * r * r * 16);
   L.gyp = take(nb * r * r * 16);
   L.qy = take(nb * r * r * 16);
   L.qy_zero = take(nb * 4);
@@ -186,6 +188,7 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.r = p.r;
   q.nb = p.n3 / 2 + 1;
   chunking(p.n1, q.nb, &q.nchunk, &q.chunk);
+  tctf::ystep_split(p.n2, p.r, q.nb, &q.ny, &q.ycw);
   q.mu = p.mu;
   q.rho1 = p.rho1;
   q.rho2 = p.rho2;
@@ -200,8 +203,11 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.yt = (float2*)(w + L.yt);
   q.rhs = (float2*)(w + L.rhs);
   q.bpart = (float2*)(w + L.bpart);
-  q.spart = (cd*)(w + L.spart);
-  q.dpart = (cd*)(w + L.dpart);
+  q.gxm = (cd*)(w + L.gxm);
+  q.dmat = (cd*)(w + L.dmat);
+  q.gxp = (cd*)(w + L.gxp);
+  q.qx = (cd*)(w + L.qx);
+  q.qx_zero = (int*)(w + L.qx_zero);
   q.gym = (cd*)(w + L.gym);
   q.gyp = (cd*)(w + L.gyp);
   q.qy = (cd*)(w + L.qy);
@@ -287,7 +293,7 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   fill_plan(c, (hipStream_t)hip_stream);
   const Plan& p = c->plan;
   tctf::slice_set_attr(p.n3, tctf::slice_lds_bytes(p.n2, p.n3));
-  tctf::ystep_set_attr(tctf::ystep_lds_bytes(p.r, p.n2));
+  tctf::ystep_set_attr(tctf::ystep_lds_bytes(p.r, p.ycw));
   tctf::bgemm_set_attr(tctf::bgemm_lds_bytes(p.r, p.chunk));
   tctf::pinvy_set_attr(p.r);
   tctf::zgemm_set_attr(p.r);

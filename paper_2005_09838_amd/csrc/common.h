@@ -118,9 +118,20 @@ __device__ __forceinline__ double block_max_d(double v, double* red) {
   return s;
 }
 
+// p[i] when ok, else z.  The load itself is unconditional (from p[0] when !ok, which must
+// be a valid element) and only its value is selected: a load under a branch is waited for
+// at the branch's end, so a batch of guarded loads would otherwise cost one memory latency
+// per load instead of one for the batch.
+template <typename T>
+__device__ __forceinline__ T ld_or(const T* __restrict__ p, size_t i, bool ok, T z) {
+  const T v = p[ok ? i : 0];
+  return ok ? v : z;
+}
+
 // Block-cooperative copy of n elements, dst[e] = load(e) for e < n, in batches of PER
 // elements per thread whose loads are all issued before any of their stores (a loop of
-// load-then-store would wait out one memory latency per element).
+// load-then-store would wait out one memory latency per element).  Lanes past n load
+// element n - 1 and drop it, so no load sits under a branch.
 template <int PER, typename T, typename F>
 __device__ __forceinline__ void stage_batched(T* dst, int n, F load) {
   const int nt = blockDim.x;
@@ -129,7 +140,7 @@ __device__ __forceinline__ void stage_batched(T* dst, int n, F load) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = e0 + threadIdx.x + u * nt;
-      if (e < n) v[u] = load(e);
+      v[u] = load(e < n ? e : n - 1);
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -148,7 +159,7 @@ __device__ __forceinline__ void stage_batched_to(int n, L load, S store) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = e0 + threadIdx.x + u * nt;
-      if (e < n) v[u] = load(e);
+      v[u] = load(e < n ? e : n - 1);
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {

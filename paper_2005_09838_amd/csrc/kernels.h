@@ -10,6 +10,7 @@ namespace tctf {
 struct Plan {
   int n1, n2, n3, r, nb;       // nb = n3/2 + 1 stored frequencies
   int nchunk, chunk;           // row chunks of the X~^* W~ reduction
+  int ny, ycw;                 // column blocks of the Y-step per frequency, columns per block
   double mu, rho1, rho2, eta;
   int mixed, force_eigen;
   hipStream_t stream;
@@ -21,9 +22,12 @@ struct Plan {
   float2* yt;       // Y~ [nb][r][n2]
   float2* rhs;      // right-hand side of the H_rho1 solve [nb][r][n1]
   float2* bpart;    // partial X~^* W~ [nb][nchunk][r][n2]
-  cd* spart;        // partial X~^* X~  [nb][nchunk][r][r]
-  cd* dpart;        // partial (H X~)^* (H X~) [nb][nchunk][r][r]
-  cd* gym;          // Y~ Y~^* [nb][r][r]
+  cd* gxm;          // G_X = X~^* H_rho1 X~ [nb][r][r]
+  cd* dmat;         // (H X~)^* (H X~) [nb][r][r]
+  cd* gxp;          // G_X^+ [nb][r][r]
+  cd* qx;           // I - eta P_X [nb][r][r]
+  int* qx_zero;     // [nb] 1 when I - eta P_X is exactly 0
+  cd* gym;          // partial Y~ Y~^* over column blocks [nb][ny][r][r]
   cd* gyp;          // (Y~ Y~^*)^+ [nb][r][r]
   cd* qy;           // I - eta P_Y [nb][r][r]
   int* qy_zero;     // [nb] 1 when I - eta P_Y is exactly 0 (eta = 1, full rank)
@@ -59,10 +63,13 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
 void launch_zgemm(const Plan& p, int with_pinv = 0);   // with_pinv: also G_Y^+ (pinvy_block)
 void launch_agemm(const Plan& p, int raw_a = 0);
 void launch_hsolve(const Plan& p);
-void launch_bgemm(const Plan& p);
+void launch_bgemm(const Plan& p);   // also G_X, G_X^+ and I - eta P_X (gramx_block)
 size_t bgemm_lds_bytes(int r, int chunk);
 void bgemm_set_attr(size_t lds);
 void launch_ystep(const Plan& p, int init);
+void ystep_split(int n2, int r, int nb, int* ny, int* cw);
+size_t ystep_lds_bytes(int r, int cw);
+void ystep_set_attr(size_t lds);
 void launch_pinvy(const Plan& p, hipStream_t stream);
 void pinvy_set_attr(int r);
 void zgemm_set_attr(int r);

@@ -10,6 +10,7 @@
 // operand that is built on the fly.  X~^* W~ is summed in FP64 over blocks of 16 rows;
 // r x r Grams and the X right-hand side epilogue are FP64.  Mixed mode reads W~ from its
 // BF16 storage and converts to FP32 before the product.
+#include <type_traits>
 #include "kernels.h"
 #include "pinv.h"
 
@@ -29,18 +30,26 @@ __device__ __forceinline__ v4d mfma4d(double a, double b, v4d c) {
 }
 
 // Two consecutive complex entries of W~ (j, j + 1) as four floats; entries past the end read 0.
-__device__ __forceinline__ float4 ld_wt2(const void* wt, size_t idx, int valid, int mixed) {
-  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (mixed) {
-    const uint32_t* w = (const uint32_t*)wt + idx;
-    if (valid > 0) { const float2 a = unpack_bf16x2(w[0]); v.x = a.x; v.y = a.y; }
-    if (valid > 1) { const float2 a = unpack_bf16x2(w[1]); v.z = a.x; v.w = a.y; }
+template <bool MIXED>
+__device__ __forceinline__ float4 ld_wt2(const void* wt, size_t idx, int valid) {
+  // both loads unconditional (as ld_or): the first from W~[0] when valid == 0, the second
+  // repeats the first when valid < 2
+  const size_t i0 = valid > 0 ? idx : 0, i1 = valid > 1 ? idx + 1 : i0;
+  float2 a, c;
+  if constexpr (MIXED) {
+    const uint32_t* w = (const uint32_t*)wt;
+    const uint32_t u0 = w[i0], u1 = w[i1];
+    a = unpack_bf16x2(u0);
+    c = unpack_bf16x2(u1);
   } else {
-    const float2* w = (const float2*)wt + idx;
-    if (valid > 0) { const float2 a = w[0]; v.x = a.x; v.y = a.y; }
-    if (valid > 1) { const float2 a = w[1]; v.z = a.x; v.w = a.y; }
+    const float2* w = (const float2*)wt;
+    a = w[i0];
+    c = w[i1];
   }
-  return v;
+  const float2 z = make_float2(0.f, 0.f);
+  if (valid < 1) a = z;
+  if (valid < 2) c = z;
+  return make_float4(a.x, a.y, c.x, c.y);
 }
 
 // ---------------------------------------------------------------- Z~ = X~ Y~
@@ -57,12 +66,10 @@ __device__ __forceinline__ float4 ld_wt2(const void* wt, size_t idx, int valid, 
 template <int RM>   // r <= RM: every loop below has a compile-time trip count
 __global__ void __launch_bounds__(256) k_zgemm(const float2* __restrict__ xt, const float2* __restrict__ yt,
                                                float2* __restrict__ zt, int n1, int n2, int r, int nb,
-                                               int npinv, const cd* __restrict__ gym, cd* __restrict__ gyp,
-                                               cd* __restrict__ qy, int* __restrict__ qy_zero, double eta,
-                                               int force_eigen) {
+                                               int npinv, PinvyArgs pa) {
   extern __shared__ __align__(16) unsigned char zsm[];
   if ((int)blockIdx.x < npinv) {
-    pinvy_block(blockIdx.x, gym, gyp, qy, qy_zero, r, eta, force_eigen, zsm);
+    pinvy_block(blockIdx.x, pa, zsm);
     return;
   }
   float2* ysh = (float2*)zsm;   // [s][j] of the column chunk
@@ -77,7 +84,7 @@ __global__ void __launch_bounds__(256) k_zgemm(const float2* __restrict__ xt, co
 #pragma unroll
     for (int u = 0; u < YPER; ++u) {
       const int e = tid + 256 * u, s = e / ZG_COLS, jj = e % ZG_COLS;
-      yv[u] = (s < r && jj < nc) ? yt[((size_t)b * r + s) * n2 + j0 + jj] : make_float2(0.f, 0.f);
+      yv[u] = ld_or(yt, ((size_t)b * r + s) * n2 + j0 + jj, s < r && jj < nc, make_float2(0.f, 0.f));
     }
   };
   load_y(0);
@@ -147,9 +154,9 @@ void launch_zgemm(const Plan& p, int with_pinv) {
   const int rm = p.r <= 8 ? 8 : (p.r <= 16 ? 16 : 32);
   size_t lds = (size_t)rm * ZG_COLS * sizeof(float2);
   if (with_pinv && pinvy_lds_bytes(p.r) > lds) lds = pinvy_lds_bytes(p.r);
-#define TCTF_ZGEMM(RM)                                                                                   \
-  k_zgemm<RM><<<grid, 256, lds, p.stream>>>(p.xt, p.yt, p.zt, p.n1, p.n2, p.r, p.nb, npinv, p.gym, p.gyp, \
-                                           p.qy, p.qy_zero, p.eta, p.force_eigen)
+  const PinvyArgs pa = pinvy_args(p);
+#define TCTF_ZGEMM(RM) \
+  k_zgemm<RM><<<grid, 256, lds, p.stream>>>(p.xt, p.yt, p.zt, p.n1, p.n2, p.r, p.nb, npinv, pa)
   if (p.r <= 8) TCTF_ZGEMM(8);
   else if (p.r <= 16) TCTF_ZGEMM(16);
   else TCTF_ZGEMM(32);
@@ -190,19 +197,24 @@ __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, cons
   for (int j0 = 0; j0 < n2; j0 += AG_COLS) {
     const int nc = min(AG_COLS, n2 - j0), ngroups = (nc + 7) / 8;
     // W~ operands of this pass: group g covers columns j0 + 8 g .. + 7; this lane takes 2
+    // (the storage branch outside the unrolled loop, so that no load waits at a join)
     float4 wa[AG_COLS / 8];
+    auto load_wa = [&](auto mixed_tag) {
 #pragma unroll
-    for (int g = 0; g < AG_COLS / 8; ++g) {
-      const int jj = 8 * g + 2 * q;
-      const int valid = (g < ngroups && row < n1) ? min(2, nc - jj) : 0;
-      wa[g] = ld_wt2(wt, ((size_t)row * nb + b) * n2 + j0 + jj, valid, mixed);
-    }
+      for (int g = 0; g < AG_COLS / 8; ++g) {
+        const int jj = 8 * g + 2 * q;
+        const int valid = (g < ngroups && row < n1) ? min(2, nc - jj) : 0;
+        wa[g] = ld_wt2<decltype(mixed_tag)::value>(wt, ((size_t)row * nb + b) * n2 + j0 + jj, valid);
+      }
+    };
+    if (mixed) load_wa(std::true_type{});
+    else load_wa(std::false_type{});
     // the Y~ column chunk, loaded while the W~ loads are in flight
     float2 yv[YPER];
 #pragma unroll
     for (int u = 0; u < YPER; ++u) {
       const int e = tid + 256 * u, s = e / AG_COLS, jj = e % AG_COLS;
-      yv[u] = (s < r && jj < nc) ? yt[((size_t)b * r + s) * n2 + j0 + jj] : make_float2(0.f, 0.f);
+      yv[u] = ld_or(yt, ((size_t)b * r + s) * n2 + j0 + jj, s < r && jj < nc, make_float2(0.f, 0.f));
     }
     if (j0 > 0) __syncthreads();   // every wavefront is done with the previous chunk
 #pragma unroll
@@ -283,16 +295,11 @@ __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, cons
         for (int v2 = 0; v2 < r; ++v2) {
           const float2* xc = xt + ((size_t)b * r + v2) * n1;
           const cd qv = qs[v2 * r + s];
-          const float2 x0 = xc[i];
+          const float2 z = make_float2(0.f, 0.f);
+          const float2 x0 = xc[i], x1 = ld_or(xc, i - 1, i > 0, z), x2 = ld_or(xc, i + 1, i + 1 < n1, z);
           cd_fma(u0, cd_make(x0.x, x0.y), qv);
-          if (i > 0) {
-            const float2 x1 = xc[i - 1];
-            cd_fma(um, cd_make(x1.x, x1.y), qv);
-          }
-          if (i + 1 < n1) {
-            const float2 x2 = xc[i + 1];
-            cd_fma(up, cd_make(x2.x, x2.y), qv);
-          }
+          cd_fma(um, cd_make(x1.x, x1.y), qv);
+          cd_fma(up, cd_make(x2.x, x2.y), qv);
         }
         t = cd_add(t, cd_sub(cd_scale(u0, dii), cd_scale(cd_add(um, up), rho1)));
       }
@@ -325,31 +332,227 @@ void launch_agemm(const Plan& p, int raw_a) {
 #undef TCTF_AGEMM
 }
 
-// ---------------------------------------------------------------- X~^* W~ and Gram partials
+// Outputs of gramx_block, per frequency b ([nb][r][r] FP64 complex unless noted).
+struct GramOut {
+  cd* gxm;       // G_X
+  cd* dmat;      // (H X~)^*(H X~)
+  cd* gxp;       // G_X^+
+  cd* qx;        // I - eta G_X^+ G_X (not written when it is exactly 0)
+  int* qx_zero;  // [nb] 1 when I - eta P_X = 0
+  double rho1, eta;
+  int force_eigen;
+};
+
+// Rows per staged group of gramx_block (plus the next row): 256 when the one sweep's
+// partials can take the staging area afterwards, 64 at r > 16.
+#define GX_ROWS(RM) ((RM) <= 16 ? 256 : 64)
+
+// LDS bytes of gramx_block at rank r <= RM: the staged rows and the complex Gram partials,
+// later G_X with the pseudo-inverse scratch.
+static inline size_t gramx_lds_bytes(int r, int rm) {
+  const int ks = rm == 8 ? 4 : 1;
+  const size_t sb = (size_t)2 * rm * (GX_ROWS(rm) + 4) * sizeof(float);
+  const size_t pb = (size_t)ks * 2 * r * r * sizeof(cd);
+  const size_t a = rm <= 16 ? (sb > pb ? sb : pb) : sb + pb;
+  return a > pinvy_lds_bytes(r) ? a : pinvy_lds_bytes(r);
+}
+
+// Frequency b, by a whole block: the FP64 Grams C = X'^T X' and the same for the row
+// differences X'(i + 1) - X'(i) over all n1 rows, as 16 x 16 x 4 FP64 matrix-core tiles.
+// Rows arrive in groups of GR (plus the next row), staged column by column (X'^T, columns
+// past 2r zero), the next group's loads in flight while the current one is multiplied.
+// Within 16 rows the K order is permuted: lane (m, q) feeds rows 4 q .. 4 q + 3 of the 16,
+// so one 16-byte LDS read (and one float of the following row) serves four steps.  Full
+// groups need no masks; the last group masks rows past n1 (and the difference at the last
+// row).  At r <= 8 the four wavefronts share the one tile and split the rows; at r > 16 each
+// wavefront takes its four tiles in two sweeps over the rows.  The lanes holding C[2s][2t]
+// gather the 2 x 2 real block by shuffles and form X~^* X~ (s, t) = (C[2s][2t] +
+// C[2s+1][2t+1], C[2s][2t+1] - C[2s+1][2t]), likewise (H X~)^*(H X~); then
+// G_X = X~^* X~ + rho1 (H X~)^*(H X~), its pseudo-inverse (Lemma SVPMPI, pinv_herm) and
+// I - eta P_X.
+template <int RM>
+__device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1, int r, const GramOut& go,
+                                   unsigned char* sm) {
+  constexpr int MT = RM / 8, NT = MT * MT;         // 16 x 16 tiles of the real Gram
+  constexpr int KS = NT >= 4 ? 1 : 4 / NT;         // wavefronts sharing a tile (row split)
+  constexpr int TPW = NT >= 4 ? NT / 4 : 1;        // tiles per wavefront
+  constexpr int TPS = TPW < 2 ? TPW : 2;           // tiles per sweep over the rows
+  constexpr int NSW = TPW / TPS;                   // sweeps
+  constexpr int GR = GX_ROWS(RM);                  // rows per group
+  constexpr int LD = GR + 4;                       // LDS stride of a staged column (floats)
+  constexpr int PER = ((GR + 1) * RM + 255) / 256; // staged elements per thread (GR + 1 rows)
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
+  const int rr = r * r, kp = KS > 1 ? w : 0;
+  float* xs = (float*)sm;   // [2 RM][LD]: X'^T, column 2 s + d of X' is row 2 s + d here
+  // [KS][2][rr]: after the staging area, or in it when one sweep leaves it free
+  cd* part = (cd*)(sm + (NSW > 1 ? (size_t)2 * RM * LD * sizeof(float) : 0));
+  // element e of a group: column s = e / (GR + 1), row h = e % (GR + 1); rows and columns
+  // past the matrix load as zeros
+  float2 pf[PER];
+  auto load_group = [&](int i0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, s = e / (GR + 1), h = e % (GR + 1);
+      pf[u] = ld_or(xt, ((size_t)b * r + s) * n1 + i0 + h, s < r && i0 + h < n1, make_float2(0.f, 0.f));
+    }
+  };
+  load_group(0);
+#pragma unroll
+  for (int sw = 0; sw < NSW; ++sw) {
+    v4d acs[TPS], acd[TPS];
+#pragma unroll
+    for (int u = 0; u < TPS; ++u) {
+      acs[u] = v4d{0.0, 0.0, 0.0, 0.0};
+      acd[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int i0 = 0; i0 < n1; i0 += GR) {
+      const int nrows = min(GR, n1 - i0);
+      __syncthreads();   // the previous rows are consumed
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = tid + 256 * u, s = e / (GR + 1), h = e % (GR + 1);
+        if (s < RM) {
+          xs[(2 * s) * LD + h] = pf[u].x;
+          xs[(2 * s + 1) * LD + h] = pf[u].y;
+        }
+      }
+      __syncthreads();
+      if (i0 + GR < n1) load_group(i0 + GR);
+      else if (sw + 1 < NSW) load_group(0);
+      const bool full = i0 + GR < n1;   // GR rows and the next one, no masks
+#pragma unroll
+      for (int u = 0; u < TPS; ++u) {
+        const int tile = KS > 1 ? 0 : w + 4 * (sw * TPS + u);
+        const float* pa = xs + (16 * (tile / MT) + m) * LD;   // column 2 s + d of X'
+        const float* pb = xs + (16 * (tile % MT) + m) * LD;
+        auto step16 = [&](int jb, auto masked) {
+          const int h0 = 16 * jb + 4 * q;
+          const float4 a4 = *(const float4*)(pa + h0), b4 = *(const float4*)(pb + h0);
+          const double av[5] = {a4.x, a4.y, a4.z, a4.w, pa[h0 + 4]};
+          const double bv[5] = {b4.x, b4.y, b4.z, b4.w, pb[h0 + 4]};
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            double a1 = av[jj + 1] - av[jj], b1 = bv[jj + 1] - bv[jj];
+            if constexpr (decltype(masked)::value) {   // the row past n1 is staged as zero
+              if (i0 + h0 + jj + 1 >= n1) a1 = b1 = 0.0;
+            }
+            acs[u] = mfma4d(av[jj], bv[jj], acs[u]);
+            acd[u] = mfma4d(a1, b1, acd[u]);
+          }
+        };
+        if (full) {
+#pragma unroll 2
+          for (int jb = kp; jb < GR / 16; jb += KS) step16(jb, std::false_type{});
+        } else {
+          for (int jb = kp; 16 * jb < nrows; jb += KS) step16(jb, std::true_type{});
+        }
+      }
+    }
+    if (NSW == 1) __syncthreads();   // the partials take the staging area
+    // element t of a lane: real row 16 ta + q + 4 t, column 16 tb + m; the lanes with q and m
+    // even hold C[2s][2t] and read C[2s][2t+1], C[2s+1][2t], C[2s+1][2t+1] from lanes + 1,
+    // + 16 and + 17
+#pragma unroll
+    for (int u = 0; u < TPS; ++u) {
+      const int tile = KS > 1 ? 0 : w + 4 * (sw * TPS + u), ta = tile / MT, tb = tile % MT;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double s0 = acs[u][t], s1 = __shfl_down(s0, 1), s16 = __shfl_down(s0, 16),
+                     s17 = __shfl_down(s0, 17);
+        const double d0 = acd[u][t], d1 = __shfl_down(d0, 1), d16 = __shfl_down(d0, 16),
+                     d17 = __shfl_down(d0, 17);
+        const int sr = (16 * ta + q + 4 * t) >> 1, sc = (16 * tb + m) >> 1;
+        if (!(q & 1) && !(m & 1) && sr < r && sc < r) {
+          part[(2 * kp) * rr + sr * r + sc] = cd_make(s0 + s17, s1 - s16);
+          part[(2 * kp + 1) * rr + sr * r + sc] = cd_make(d0 + d17, d1 - d16);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int GPT = (RM * RM + 255) / 256;   // G_X entries per thread
+  cd gv[GPT];
+#pragma unroll
+  for (int k = 0; k < GPT; ++k) {
+    const int e = tid + 256 * k;
+    gv[k] = cd_make(0.0, 0.0);
+    if (e < rr) {
+      cd sv = part[e], dv = part[rr + e];
+#pragma unroll
+      for (int j = 1; j < KS; ++j) {   // the row parts, in a fixed order
+        sv = cd_add(sv, part[2 * j * rr + e]);
+        dv = cd_add(dv, part[(2 * j + 1) * rr + e]);
+      }
+      gv[k] = cd_add(sv, cd_scale(dv, go.rho1));
+      go.gxm[(size_t)b * rr + e] = gv[k];
+      go.dmat[(size_t)b * rr + e] = dv;
+    }
+  }
+  __syncthreads();   // the partials are read; G_X and the pinv scratch take their place
+  cd* gx = (cd*)sm;
+  cd* gp = gx + rr;
+  PinvScratch ps;
+  ps.work = gp + rr;
+  ps.vec = ps.work + rr;
+  ps.colk = ps.vec + rr;
+  ps.rowk = ps.colk + r;
+  ps.rot = (double*)(ps.rowk + r);
+  ps.red = ps.rot + 96;
+#pragma unroll
+  for (int k = 0; k < GPT; ++k) {
+    const int e = tid + 256 * k;
+    if (e < rr) gx[e] = gv[k];
+  }
+  __syncthreads();
+  const int full = pinv_herm(gx, gp, r, go.force_eigen, ps);
+  const bool qzero = full && go.eta == 1.0;
+  for (int e = tid; e < rr; e += 256) {
+    go.gxp[(size_t)b * rr + e] = gp[e];
+    if (!qzero) {   // q = I - eta G_X^+ G_X
+      const int s = e / r, t = e % r;
+      cd acc = cd_make(0.0, 0.0);
+      for (int u = 0; u < r; ++u) cd_fma(acc, gp[s * r + u], gx[u * r + t]);
+      go.qx[(size_t)b * rr + e] = cd_make((s == t ? 1.0 : 0.0) - go.eta * acc.re, -go.eta * acc.im);
+    }
+  }
+  if (tid == 0) go.qx_zero[b] = qzero ? 1 : 0;
+}
+
+// ---------------------------------------------------------------- X~^* W~, and G_X with its inverse
 // Real form: C'[2s + d][2j + c] = sum_i X'[2s + d][i] W'[i][2j + c] with X'[2s + d][i] =
 // (re, im)_d X~(i, s) and W' the interleaved W~ rows; then
 // (X~^* W~)(s, j) = (C'[2s][2j] + C'[2s+1][2j+1], C'[2s][2j+1] - C'[2s+1][2j]).
-// Block: one chunk of at most 64 rows x one frequency.  The chunk's X~ rows (plus the
-// next row, for H X~) and, per pass of BG_COLS columns, its whole W~ slab are staged in
-// LDS with every load of a thread issued at once; each wavefront owns a quarter of the
-// 16-column tiles of a pass.  After every 16 rows the FP32 tile sums are added into FP64
-// accumulators.  The FP64 Gram partials of the chunk are formed from the staged X~ rows.
+// Block: one chunk of at most 64 rows x one frequency.  The chunk's X~ rows and, per pass
+// of BG_COLS columns, its whole W~ slab are staged in LDS with every load of a thread
+// issued at once; each wavefront owns a quarter of the 16-column tiles of a pass.  After
+// every 16 rows the FP32 tile sums are added into FP64 accumulators.
+// At r <= 16 the first nb blocks of the launch instead form, for frequency blockIdx.x, the
+// whole Gram G_X = X~^* X~ + rho1 (H X~)^*(H X~) in FP64 on the matrix cores, its
+// pseudo-inverse and I - eta P_X (gramx_block): the Y-step needs them, and they run beside
+// the products; at r > 16 k_gramx does this work in a launch of its own.
 #define BG_COLS 64                  // complex columns per pass
 #define BG_MAXROWS 64               // rows per chunk at most
 #define BG_WLD (2 * BG_COLS + 16)   // LDS row stride of the staged W~ slab (floats)
-template <int RM>   // r <= RM
-__global__ void __launch_bounds__(256) k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt,
-                                               float2* __restrict__ bpart, cd* __restrict__ spart,
-                                               cd* __restrict__ dpart, int n1, int n2, int r, int nb,
-                                               int nchunk, int chunk, int mixed) {
+template <int RM>   // r <= RM; registers and LDS allow three blocks per compute unit at r <= 16
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RM <= 16 ? 2 : 1)))
+k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, float2* __restrict__ bpart, GramOut go, int n1,
+        int n2, int r, int nb, int nchunk, int chunk, int mixed) {
   extern __shared__ __align__(16) float smb[];
+  constexpr bool GRAM = RM <= 16;   // at r > 16 the registers of both paths would not fit twice
+  const int ng = GRAM ? nb : 0;     // G_X blocks at the front of the grid
+  if constexpr (GRAM) {
+    if ((int)blockIdx.x < nb) {
+      gramx_block<RM>(blockIdx.x, xt, n1, r, go, (unsigned char*)smb);
+      return;
+    }
+  }
   const int xld = 2 * r + 16;                    // LDS row stride of the staged X~ rows (floats)
   float* xs = smb;                               // [chunk + 1][xld]: (re, im) of X~(i, s) at 2 s
   float* ws = smb + (size_t)(chunk + 1) * xld;   // [chunk rounded up to 4][BG_WLD]
-  const int c = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int c = ((int)blockIdx.x - ng) % nchunk, b = ((int)blockIdx.x - ng) / nchunk, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
   const int i0 = c * chunk, i1 = min(n1, i0 + chunk), nrows = i1 - i0;
-  const int rows = nrows + ((i1 < n1) ? 1 : 0);
+  const int rows = nrows;
   const int nks = (nrows + 3) / 4;   // K steps of 4 rows
   // W~ slab of one pass: rows i0 .. i1 - 1 (zeros up to a multiple of 4), columns
   // j0 .. j0 + nc - 1; 16 elements per thread, loaded into registers ahead of their use
@@ -357,13 +560,20 @@ __global__ void __launch_bounds__(256) k_bgemm(const void* __restrict__ wt, cons
   float2 slab[SLAB_PER];
   auto load_slab = [&](int j0) {
     const int nc = min(BG_COLS, n2 - j0);
+    // (the storage branch outside the unrolled loops, so that no load waits at a join)
+    if (mixed) {
 #pragma unroll
-    for (int u = 0; u < SLAB_PER; ++u) {
-      const int e = tid + 256 * u, rr = e / BG_COLS, jj = e % BG_COLS;
-      slab[u] = make_float2(0.f, 0.f);
-      if (rr < nrows && jj < nc) {
+      for (int u = 0; u < SLAB_PER; ++u) {
+        const int e = tid + 256 * u, rr = e / BG_COLS, jj = e % BG_COLS;
         const size_t idx = ((size_t)(i0 + rr) * nb + b) * n2 + j0 + jj;
-        slab[u] = mixed ? unpack_bf16x2(((const uint32_t*)wt)[idx]) : ((const float2*)wt)[idx];
+        slab[u] = unpack_bf16x2(ld_or((const uint32_t*)wt, idx, rr < nrows && jj < nc, 0u));
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < SLAB_PER; ++u) {
+        const int e = tid + 256 * u, rr = e / BG_COLS, jj = e % BG_COLS;
+        const size_t idx = ((size_t)(i0 + rr) * nb + b) * n2 + j0 + jj;
+        slab[u] = ld_or((const float2*)wt, idx, rr < nrows && jj < nc, make_float2(0.f, 0.f));
       }
     }
   };
@@ -454,52 +664,22 @@ __global__ void __launch_bounds__(256) k_bgemm(const void* __restrict__ wt, cons
       }
     }
   }
-  // Gram partials of the chunk in FP64 on the matrix cores: C = X'^T X' and the same for the
-  // row differences X'(i + 1) - X'(i) (rows whose successor exists), 2r x 2r real tiles of
-  // 16 x 16 over K = the chunk's rows; then X~^* X~ (s, t) = (C[2s][2t] + C[2s+1][2t+1],
-  // C[2s][2t+1] - C[2s+1][2t]) and the same for (H X~)^*(H X~).
-  __syncthreads();   // the W~ slab area is free: the tiles go there
-  double* cs = (double*)ws;                 // [2 RM][2 RM]
-  double* cdm = cs + 4 * RM * RM;           // [2 RM][2 RM]
-  for (int tile = w; tile < MT * MT; tile += 4) {
-    const int ta = tile / MT, tb = tile % MT;
-    v4d accs = v4d{0.0, 0.0, 0.0, 0.0}, accd = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int ks = 0; ks < nks; ++ks) {
-      const int kr = 4 * ks + q;              // chunk row of this lane's K index
-      const bool in = kr < nrows, hasnext = in && i0 + kr + 1 < n1;
-      const int ca = 16 * ta + m, cb = 16 * tb + m;   // columns 2 s + d of X'
-      const bool va = ca < 2 * r, vb = cb < 2 * r;
-      const float* x0 = xs + (size_t)kr * xld;
-      const double a0 = (in && va) ? (double)x0[ca] : 0.0, b0 = (in && vb) ? (double)x0[cb] : 0.0;
-      const double a1 = (hasnext && va) ? (double)x0[xld + ca] - a0 : 0.0;
-      const double b1 = (hasnext && vb) ? (double)x0[xld + cb] - b0 : 0.0;
-      accs = mfma4d(a0, b0, accs);
-      accd = mfma4d(a1, b1, accd);
-    }
-    // element t of the FP64 tile is row 16 ta + q + 4 t, column 16 tb + m
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int rw = 16 * ta + q + 4 * t, cl = 16 * tb + m;
-      cs[rw * 2 * RM + cl] = accs[t];
-      cdm[rw * 2 * RM + cl] = accd[t];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < r * r; e += 256) {
-    const int s = e / r, t = e % r;
-    const int r0 = 2 * s * 2 * RM, r1 = (2 * s + 1) * 2 * RM;
-    spart[(((size_t)b * nchunk + c) * r) * r + e] =
-        cd_make(cs[r0 + 2 * t] + cs[r1 + 2 * t + 1], cs[r0 + 2 * t + 1] - cs[r1 + 2 * t]);
-    dpart[(((size_t)b * nchunk + c) * r) * r + e] =
-        cd_make(cdm[r0 + 2 * t] + cdm[r1 + 2 * t + 1], cdm[r0 + 2 * t + 1] - cdm[r1 + 2 * t]);
-  }
+}
+
+// G_X alone, one block per frequency (r > 16: beside the products it would cost them
+// registers).
+template <int RM>
+__global__ void __launch_bounds__(256) k_gramx(const float2* __restrict__ xt, GramOut go, int n1, int r) {
+  extern __shared__ __align__(16) unsigned char smg[];
+  gramx_block<RM>(blockIdx.x, xt, n1, r, go, smg);
 }
 
 size_t bgemm_lds_bytes(int r, int chunk) {
   const int rm = r <= 8 ? 8 : (r <= 16 ? 16 : 32);
   const size_t slab = (size_t)((chunk + 3) / 4 * 4) * BG_WLD * sizeof(float);
-  const size_t tiles = 2 * (size_t)(2 * rm) * (2 * rm) * sizeof(double);   // the FP64 Gram tiles
-  return (size_t)(chunk + 1) * (2 * r + 16) * sizeof(float) + (slab > tiles ? slab : tiles);
+  const size_t chunkb = (size_t)(chunk + 1) * (2 * r + 16) * sizeof(float) + slab;
+  const size_t gram = gramx_lds_bytes(r, rm);
+  return chunkb > gram ? chunkb : gram;
 }
 
 void bgemm_set_attr(size_t lds) {
@@ -507,18 +687,34 @@ void bgemm_set_attr(size_t lds) {
     (void)hipFuncSetAttribute((const void*)k_bgemm<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute((const void*)k_bgemm<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute((const void*)k_bgemm<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_gramx<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
 }
 
 void launch_bgemm(const Plan& p) {
-  dim3 grid(p.nchunk, p.nb);
+  const bool fused = p.r <= 16;
+  const int grid = (fused ? p.nb : 0) + p.nchunk * p.nb;   // G_X blocks first, then (chunk, frequency)
   const size_t lds = bgemm_lds_bytes(p.r, p.chunk);
-#define TCTF_BGEMM(RM)                                                                                      \
-  k_bgemm<RM><<<grid, 256, lds, p.stream>>>(p.wt, p.xt, p.bpart, p.spart, p.dpart, p.n1, p.n2, p.r, p.nb, \
-                                            p.nchunk, p.chunk, p.mixed)
-  if (p.r <= 8) TCTF_BGEMM(8);
-  else if (p.r <= 16) TCTF_BGEMM(16);
-  else TCTF_BGEMM(32);
+  GramOut go;
+  go.gxm = p.gxm;
+  go.dmat = p.dmat;
+  go.gxp = p.gxp;
+  go.qx = p.qx;
+  go.qx_zero = p.qx_zero;
+  go.rho1 = p.rho1;
+  go.eta = p.eta;
+  go.force_eigen = p.force_eigen;
+#define TCTF_BGEMM(RM)                                                                                  \
+  k_bgemm<RM><<<grid, 256, lds, p.stream>>>(p.wt, p.xt, p.bpart, go, p.n1, p.n2, p.r, p.nb, p.nchunk, \
+                                            p.chunk, p.mixed)
+  if (p.r <= 8) {
+    TCTF_BGEMM(8);
+  } else if (p.r <= 16) {
+    TCTF_BGEMM(16);
+  } else {
+    k_gramx<32><<<p.nb, 256, lds, p.stream>>>(p.xt, go, p.n1, p.r);
+    TCTF_BGEMM(32);
+  }
 #undef TCTF_BGEMM
 }
 

@@ -169,223 +169,151 @@ void launch_hsolve(const Plan& p) {
   k_hsolve<<<p.nb * p.r * 2, 64, lds, p.stream>>>(p.rhs, p.htab, p.xt, p.n1, p.r, p.n3);
 }
 
-// Dynamic LDS layout of k_ystep (r x r FP64 complex matrices unless noted); jb columns of
-// Y~ are handled per block step.
-#define YS_THREADS 512
-#define YS_LDS_BUDGET (150 * 1024)
+// Dynamic LDS layout of k_ystep (r x r FP64 complex matrices, then the column block of
+// cw columns with an odd row stride cw | 1, so that the rows of one column fall in
+// different LDS banks).
+#define YS_CP 8   // chunk partials of X~^* W~ loaded together
 struct YLayout {
-  size_t gx, dm, gp, q, gy, gpart, work, vec, colk, rowk, rot, red, bsum, yold, ynew, total;
+  size_t gp, q, bsum, yold, ynew, total;
 };
-__host__ __device__ inline YLayout ystep_layout(int r, int jb) {
+__host__ __device__ inline YLayout ystep_layout(int r, int cw) {
   YLayout L;
-  const size_t m = (size_t)r * r * sizeof(cd);
-  const size_t npart = (size_t)(r * r < YS_THREADS ? YS_THREADS : r * r);
+  const size_t m = (size_t)r * r * sizeof(cd), ld = (size_t)(cw | 1);
   size_t o = 0;
-  L.gx = o; o += m;
-  L.dm = o; o += m;
   L.gp = o; o += m;
   L.q = o; o += m;
-  L.gy = o; o += m;
-  L.gpart = o; o += npart * sizeof(cd);                 // partial Gram sums of one block step
-  L.work = o; o += m;
-  L.vec = o; o += m;
-  L.colk = o; o += r * sizeof(cd);
-  L.rowk = o; o += r * sizeof(cd);
-  L.rot = o; o += 96 * sizeof(double);
-  L.red = o; o += 16 * sizeof(double);
-  // the column blocks below have a row stride of (jb | 1): odd, so the rows of one column
-  // fall in different LDS banks
-  const size_t ld = (size_t)(jb | 1);
-  L.bsum = o; o += (size_t)r * ld * sizeof(cd);         // columns of X~^* W~ (FP64)
-  L.yold = o; o += (size_t)r * ld * sizeof(float2);     // the same columns of the old Y~
-  L.ynew = o; o += (size_t)r * ld * sizeof(float2);     // and of the new (stored) Y~
+  L.bsum = o; o += (size_t)r * ld * sizeof(cd);       // columns of X~^* W~ (FP64)
+  L.yold = o; o += (size_t)r * ld * sizeof(float2);   // the same columns of the old Y~
+  L.ynew = o; o += (size_t)r * ld * sizeof(float2);   // and of the new (stored) Y~
   L.total = o;
   return L;
 }
 
-// Columns per block step: all of n2 when they fit the LDS budget, else as many as fit.
-static int ystep_jb(int r, int n2) {
-  const size_t fixed = ystep_layout(r, 0).total;
-  const size_t per = (size_t)r * (sizeof(cd) + 2 * sizeof(float2));
-  int jb = (int)((YS_LDS_BUDGET - fixed) / per) - 1;
-  if (jb > n2) jb = n2;
-  if (jb < 1) jb = 1;
-  return jb;
+// Column blocks of the Y-step: enough blocks to cover the compute units, at least 8 columns
+// each, at most 1024 / r (four elements per thread).
+void ystep_split(int n2, int r, int nb, int* ny, int* cw) {
+  const int want = (256 + nb - 1) / nb;
+  int c = (n2 + want - 1) / want;
+  if (c < 8) c = 8;
+  if (c > 1024 / r) c = 1024 / r;
+  if (c > n2) c = n2;
+  *cw = c;
+  *ny = (n2 + c - 1) / c;
 }
 
-// One block per frequency.  Y~ is visited in blocks of jb columns: the chunk partials of
-// X~^* W~ and the old columns are loaded together (independent loads, summed in a fixed
-// order), the new columns are formed in FP64 and stored in FP32, and their FP64 Gram is
-// accumulated from the stored values, so Y~ is read once and written once.  When a
-// pseudo-inverse keeps every eigenvalue and eta = 1, I - eta P is exactly 0 and is not
-// formed.
-__global__ void __launch_bounds__(YS_THREADS) k_ystep(float2* __restrict__ yt, const float2* __restrict__ bpart,
-                                                      const cd* __restrict__ spart, const cd* __restrict__ dpart,
-                                                      cd* __restrict__ gy_out, double* __restrict__ bin_obj,
-                                                      int n2, int r, int n3, int nchunk, int jb, double eta,
-                                                      double rho1, int force_eigen, int init) {
+// Block (column block jb, frequency b), 256 threads; G_X^+ and I - eta P_X come from the
+// X~^* W~ launch (gramx_block).  The chunk partials of X~^* W~ for the block's columns and the
+// old columns are loaded together (independent loads, summed in a fixed order), the new
+// columns Y~ <- (I - eta P_X) Y~ + eta G_X^+ X~^* W~ (eq. (updataXYW1)) are formed in FP64 and
+// stored in FP32, and the block's FP64 partial of G_Y = Y~ Y~^* is formed from the stored
+// values.  init: only the partial of G_Y.
+__global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const float2* __restrict__ bpart,
+                                               const cd* __restrict__ gxp, const cd* __restrict__ qx,
+                                               const int* __restrict__ qx_zero, cd* __restrict__ gyq, int n2,
+                                               int r, int n3, int nchunk, int cw, int ny, double eta, int init) {
   extern __shared__ __align__(16) unsigned char sm[];
-  const YLayout L = ystep_layout(r, jb);
-  cd* gx = (cd*)(sm + L.gx);
-  cd* dm = (cd*)(sm + L.dm);
+  const YLayout L = ystep_layout(r, cw);
   cd* gp = (cd*)(sm + L.gp);
   cd* q = (cd*)(sm + L.q);
-  cd* gy = (cd*)(sm + L.gy);
-  cd* gpart = (cd*)(sm + L.gpart);
-  PinvScratch ps;
-  ps.work = (cd*)(sm + L.work);
-  ps.vec = (cd*)(sm + L.vec);
-  ps.colk = (cd*)(sm + L.colk);
-  ps.rowk = (cd*)(sm + L.rowk);
-  ps.rot = (double*)(sm + L.rot);
-  ps.red = (double*)(sm + L.red);
   cd* bsum = (cd*)(sm + L.bsum);
   float2* yold = (float2*)(sm + L.yold);
   float2* ynew = (float2*)(sm + L.ynew);
-  const int b = blockIdx.x, tid = threadIdx.x, rr = r * r, nt = YS_THREADS;
+  const int jb = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, rr = r * r;
+  const int j0 = jb * cw, nj = min(cw, n2 - j0), nel = r * nj, ld = cw | 1;
   const bool real_bin = bin_is_real(b, n3);
-  const int ld = jb | 1;
+  const bool qzero = init || qx_zero[b] != 0;
+  const float2 z2 = make_float2(0.f, 0.f);
+  const cd zc = cd_make(0.0, 0.0);
 
-  // One batch of column-block elements per thread (four in flight): the old Y~ entries and
-  // the sums of the X~^* W~ chunk partials (fixed order).
+  // every load of the block issued before any use: old columns, chunk partials (YS_CP at a
+  // time), G_X^+ and q
   float2 y[4];
   cd acc[4];
-  auto load_batch = [&](int j0, int nj, int e0) {
-    const int nel = r * nj;
+  size_t base[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + tid + u * nt;
-      y[u] = make_float2(0.f, 0.f);
-      acc[u] = cd_make(0.0, 0.0);
-      if (e < nel) {
-        const int t = e / nj, jj = e % nj;
-        y[u] = yt[((size_t)b * r + t) * n2 + j0 + jj];
-        if (!init) {
-          const float2* bp = bpart + ((size_t)b * nchunk * r + t) * n2 + j0 + jj;
-#pragma unroll 8
-          for (int c = 0; c < nchunk; ++c) {
-            const float2 v = bp[(size_t)c * r * n2];
-            acc[u].re += v.x;
-            acc[u].im += v.y;
-          }
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, t = e / nj, jj = e % nj;
+    base[u] = ((size_t)b * nchunk * r + t) * n2 + j0 + jj;
+    y[u] = ld_or(yt, ((size_t)b * r + t) * n2 + j0 + jj, e < nel, z2);
+    acc[u] = zc;
+  }
+  cd g4[4], q4[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u;
+    g4[u] = ld_or(gxp, (size_t)b * rr + e, !init && e < rr, zc);
+    q4[u] = ld_or(qx, (size_t)b * rr + e, !qzero && e < rr, zc);
+  }
+  if (!init) {
+    for (int c0 = 0; c0 < nchunk; c0 += YS_CP) {
+      float2 v[4][YS_CP];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < YS_CP; ++k)
+          v[u][k] = ld_or(bpart, base[u] + (size_t)(c0 + k) * r * n2, tid + 256 * u < nel && c0 + k < nchunk, z2);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < YS_CP; ++k) {
+          acc[u].re += v[u][k].x;
+          acc[u].im += v[u][k].y;
         }
-      }
     }
-  };
-  auto store_batch = [&](int nj, int e0) {
-    const int nel = r * nj;
+  }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + tid + u * nt;
-      if (e < nel) {
-        const int t = e / nj, jj = e % nj;
-        yold[t * ld + jj] = y[u];
-        bsum[t * ld + jj] = acc[u];
-      }
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u;
+    if (e < nel) {
+      const int t = e / nj, jj = e % nj;
+      yold[t * ld + jj] = y[u];
+      bsum[t * ld + jj] = acc[u];
     }
-  };
-  // when the first column block is one batch, its loads are issued before the G_X work
-  const int nj0 = min(jb, n2);
-  const bool early = r * nj0 <= 4 * nt;
-  if (early) load_batch(0, nj0, 0);
-
-  // G_X = S + rho1 D from the chunk partials (fixed order)
-  for (int e = tid; e < rr; e += nt) {
-    cd sacc = cd_make(0.0, 0.0), dacc = cd_make(0.0, 0.0);
-#pragma unroll 4
-    for (int c = 0; c < nchunk; ++c) {
-      sacc = cd_add(sacc, spart[((size_t)b * nchunk + c) * rr + e]);
-      dacc = cd_add(dacc, dpart[((size_t)b * nchunk + c) * rr + e]);
+    if (e < rr) {
+      gp[e] = g4[u];
+      q[e] = q4[u];
     }
-    dm[e] = dacc;
-    gx[e] = cd_add(sacc, cd_scale(dacc, rho1));
-    gy[e] = cd_make(0.0, 0.0);
   }
   __syncthreads();
-
-  bool qzero = true;
   if (!init) {
-    const int full = pinv_herm(gx, gp, r, force_eigen, ps);
-    qzero = full && eta == 1.0;
-    if (!qzero) {   // q = I - eta G_X^+ G_X
-      for (int e = tid; e < rr; e += nt) {
-        const int s = e / r, t = e % r;
-        cd acc = cd_make(0.0, 0.0);
-        for (int u = 0; u < r; ++u) cd_fma(acc, gp[s * r + u], gx[u * r + t]);
-        q[e] = cd_make((s == t ? 1.0 : 0.0) - eta * acc.re, -eta * acc.im);
-      }
-      __syncthreads();
-    }
-  }
-  const int np = rr < nt ? nt / rr : 1;   // partial sums per Gram entry
-  for (int j0 = 0; j0 < n2; j0 += jb) {
-    const int nj = min(jb, n2 - j0), nel = r * nj;
-    for (int e0 = 0; e0 < nel; e0 += 4 * nt) {
-      if (!(early && j0 == 0)) load_batch(j0, nj, e0);
-      store_batch(nj, e0);
-    }
-    __syncthreads();
-    if (!init) {
-      // Y~ <- q Y~ + eta G_X^+ B on these columns
-      for (int e = tid; e < nel; e += nt) {
-        const int s = e / nj, jj = e % nj;
-        cd acc = cd_make(0.0, 0.0), acc2 = cd_make(0.0, 0.0);
+    for (int e = tid; e < nel; e += 256) {
+      const int s = e / nj, jj = e % nj;
+      cd a1 = zc, a2 = zc;
 #pragma unroll 4
-        for (int t = 0; t < r; ++t) cd_fma(acc2, gp[s * r + t], bsum[t * ld + jj]);
-        if (!qzero) {
+      for (int t = 0; t < r; ++t) cd_fma(a2, gp[s * r + t], bsum[t * ld + jj]);
+      if (!qzero) {
 #pragma unroll 4
-          for (int t = 0; t < r; ++t) {
-            const float2 y = yold[t * ld + jj];
-            cd_fma(acc, q[s * r + t], cd_make(y.x, y.y));
-          }
+        for (int t = 0; t < r; ++t) {
+          const float2 yv = yold[t * ld + jj];
+          cd_fma(a1, q[s * r + t], cd_make(yv.x, yv.y));
         }
-        acc = cd_add(acc, cd_scale(acc2, eta));
-        const float2 v = make_float2((float)acc.re, real_bin ? 0.0f : (float)acc.im);
-        ynew[s * ld + jj] = v;
-        yt[((size_t)b * r + s) * n2 + j0 + jj] = v;
       }
-      __syncthreads();
-    }
-    // G_Y += (stored columns) (stored columns)^*, np interleaved partial sums per entry
-    const float2* yb = init ? yold : ynew;
-    for (int e2 = tid; e2 < rr * np; e2 += nt) {
-      const int e = e2 % rr, part = e2 / rr, s = e / r, t = e % r;
-      cd acc = cd_make(0.0, 0.0);
-#pragma unroll 4
-      for (int jj = part; jj < nj; jj += np) {
-        const float2 u = yb[s * ld + jj], v = yb[t * ld + jj];
-        cd_fma(acc, cd_make(u.x, u.y), cd_make(v.x, -v.y));
-      }
-      gpart[e2] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < rr; e += nt) {
-      cd acc = gy[e];
-      for (int part = 0; part < np; ++part) acc = cd_add(acc, gpart[part * rr + e]);
-      gy[e] = acc;
+      a1 = cd_add(a1, cd_scale(a2, eta));
+      const float2 v = make_float2((float)a1.re, real_bin ? 0.0f : (float)a1.im);
+      ynew[s * ld + jj] = v;
+      yt[((size_t)b * r + s) * n2 + j0 + jj] = v;
     }
     __syncthreads();
   }
-
-  // G_Y for k_pinvy, and c_b tr(D G_Y): the rho1 term of eq. (fun-XYW) for this frequency
-  double tr = 0.0;
-  for (int e = tid; e < rr; e += nt) {
+  // partial G_Y(s, t) = sum over the block's columns of Y~(s, j) conj(Y~(t, j)), stored values
+  const float2* yb = init ? yold : ynew;
+  for (int e = tid; e < rr; e += 256) {
     const int s = e / r, t = e % r;
-    gy_out[(size_t)b * rr + e] = gy[e];
-    const cd d = dm[s * r + t], g = gy[t * r + s];
-    tr += d.re * g.re - d.im * g.im;
+    cd g = zc;
+#pragma unroll 4
+    for (int jj = 0; jj < nj; ++jj) {
+      const float2 u = yb[s * ld + jj], v = yb[t * ld + jj];
+      cd_fma(g, cd_make(u.x, u.y), cd_make(v.x, -v.y));
+    }
+    gyq[((size_t)b * ny + jb) * rr + e] = g;
   }
-  tr = block_sum_d(tr, ps.red);
-  if (tid == 0) bin_obj[b] = bin_weight(b, n3) * tr;
 }
 
 // Per frequency: G_Y^+ and I - eta P_Y (pinvy_block).  In the iteration this work rides
 // along the Z~ product (k_zgemm); this kernel serves create and stage timing.
-__global__ void __launch_bounds__(256) k_pinvy(const cd* __restrict__ gy_in, cd* __restrict__ gyp_out,
-                                               cd* __restrict__ qy_out, int* __restrict__ qy_zero, int r,
-                                               double eta, int force_eigen) {
+__global__ void __launch_bounds__(256) k_pinvy(PinvyArgs pa) {
   extern __shared__ __align__(16) unsigned char psm[];
-  pinvy_block(blockIdx.x, gy_in, gyp_out, qy_out, qy_zero, r, eta, force_eigen, psm);
+  pinvy_block(blockIdx.x, pa, psm);
 }
 
 void pinvy_set_attr(int r) {
@@ -395,10 +323,10 @@ void pinvy_set_attr(int r) {
 }
 
 void launch_pinvy(const Plan& p, hipStream_t stream) {
-  k_pinvy<<<p.nb, 256, pinvy_lds_bytes(p.r), stream>>>(p.gym, p.gyp, p.qy, p.qy_zero, p.r, p.eta, p.force_eigen);
+  k_pinvy<<<p.nb, 256, pinvy_lds_bytes(p.r), stream>>>(pinvy_args(p));
 }
 
-size_t ystep_lds_bytes(int r, int n2) { return ystep_layout(r, ystep_jb(r, n2)).total; }
+size_t ystep_lds_bytes(int r, int cw) { return ystep_layout(r, cw).total; }
 
 void ystep_set_attr(size_t lds) {
   if (lds > 65536)
@@ -406,10 +334,9 @@ void ystep_set_attr(size_t lds) {
 }
 
 void launch_ystep(const Plan& p, int init) {
-  const int jb = ystep_jb(p.r, p.n2);
-  const size_t lds = ystep_layout(p.r, jb).total;
-  k_ystep<<<p.nb, YS_THREADS, lds, p.stream>>>(p.yt, p.bpart, p.spart, p.dpart, p.gym, p.bin_obj, p.n2, p.r,
-                                               p.n3, p.nchunk, jb, p.eta, p.rho1, p.force_eigen, init);
+  const size_t lds = ystep_layout(p.r, p.ycw).total;
+  k_ystep<<<dim3(p.ny, p.nb), 256, lds, p.stream>>>(p.yt, p.bpart, p.gxp, p.qx, p.qx_zero, p.gym, p.n2, p.r, p.n3,
+                                                   p.nchunk, p.ycw, p.ny, p.eta, init);
 }
 
 }  // namespace tctf

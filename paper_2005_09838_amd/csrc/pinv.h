@@ -13,6 +13,7 @@
 // and the rule is applied to its eigenvalues.
 #pragma once
 #include "common.h"
+#include "kernels.h"
 
 #define TCTF_EPS64 2.220446049250313e-16
 
@@ -294,13 +295,43 @@ __host__ __device__ inline size_t pinvy_lds_bytes(int r) {
   return (size_t)(4 * r * r + 2 * r) * sizeof(cd) + 144 * sizeof(double);
 }
 
-// Per frequency b, by a whole block: G_Y^+ from the Gram G_Y in gym and, unless it is
-// exactly 0, q = I - eta G_Y G_Y^+ for the next X-update (first line of eq. (updataXYW1));
-// qy_zero[b] = 1 marks q = 0.  sm: pinvy_lds_bytes(r) bytes of LDS.
-__device__ inline void pinvy_block(int b, const cd* __restrict__ gym, cd* __restrict__ gyp, cd* __restrict__ qy,
-                                   int* __restrict__ qy_zero, int r, double eta, int force_eigen,
-                                   unsigned char* sm) {
-  const int tid = threadIdx.x, nt = blockDim.x, rr = r * r;
+// Inputs and outputs of pinvy_block ([nb][r][r] FP64 complex unless noted).
+struct PinvyArgs {
+  const cd* gyq;      // [nb][ny][r][r] partial Grams of Y~ over column blocks
+  int ny;
+  const cd* dmat;     // (H X~)^*(H X~)
+  double* bin_obj;    // [nb] c_b tr((H X~)^*(H X~) G_Y): the rho1 term of eq. (fun-XYW)
+  int n3;
+  cd* gyp;            // G_Y^+
+  cd* qy;             // I - eta P_Y
+  int* qy_zero;       // [nb] 1 when I - eta P_Y is exactly 0
+  int r;
+  double eta;
+  int force_eigen;
+};
+
+static inline PinvyArgs pinvy_args(const tctf::Plan& p) {
+  PinvyArgs a;
+  a.gyq = p.gym;
+  a.ny = p.ny;
+  a.dmat = p.dmat;
+  a.bin_obj = p.bin_obj;
+  a.n3 = p.n3;
+  a.gyp = p.gyp;
+  a.qy = p.qy;
+  a.qy_zero = p.qy_zero;
+  a.r = p.r;
+  a.eta = p.eta;
+  a.force_eigen = p.force_eigen;
+  return a;
+}
+
+// Per frequency b, by a whole block: G_Y as the sum of the column-block partials (fixed
+// order), the objective term c_b tr(D G_Y), G_Y^+ and, unless it is exactly 0,
+// q = I - eta G_Y G_Y^+ for the next X-update (first line of eq. (updataXYW1)); qy_zero[b] = 1
+// marks q = 0.  sm: pinvy_lds_bytes(r) bytes of LDS.
+__device__ inline void pinvy_block(int b, const PinvyArgs& a, unsigned char* sm) {
+  const int tid = threadIdx.x, nt = blockDim.x, r = a.r, rr = r * r;
   cd* gy = (cd*)sm;
   cd* gp = gy + rr;
   PinvScratch ps;
@@ -310,20 +341,28 @@ __device__ inline void pinvy_block(int b, const cd* __restrict__ gym, cd* __rest
   ps.rowk = ps.colk + r;
   ps.rot = (double*)(ps.rowk + r);
   ps.red = ps.rot + 96;
-  for (int e = tid; e < rr; e += nt) gy[e] = gym[(size_t)b * rr + e];
-  __syncthreads();
-  const int fully = pinv_herm(gy, gp, r, force_eigen, ps);
-  const bool qyz = fully && eta == 1.0;
+  double tr = 0.0;
+  for (int e = tid; e < rr; e += nt) {
+    cd g = a.gyq[(size_t)b * a.ny * rr + e];
+    for (int k = 1; k < a.ny; ++k) g = cd_add(g, a.gyq[((size_t)b * a.ny + k) * rr + e]);
+    gy[e] = g;
+    const cd d = a.dmat[(size_t)b * rr + (e % r) * r + e / r];   // D(t, s) for G_Y(s, t)
+    tr += d.re * g.re - d.im * g.im;
+  }
+  tr = block_sum_d(tr, ps.red);   // also orders the G_Y stores before their reads
+  if (tid == 0) a.bin_obj[b] = bin_weight(b, a.n3) * tr;
+  const int fully = pinv_herm(gy, gp, r, a.force_eigen, ps);
+  const bool qyz = fully && a.eta == 1.0;
   for (int e = tid; e < rr; e += nt) {
     cd qv = cd_make(0.0, 0.0);
     if (!qyz) {
       const int s = e / r, t = e % r;
       cd acc = cd_make(0.0, 0.0);
       for (int u = 0; u < r; ++u) cd_fma(acc, gy[s * r + u], gp[u * r + t]);
-      qv = cd_make((s == t ? 1.0 : 0.0) - eta * acc.re, -eta * acc.im);
+      qv = cd_make((s == t ? 1.0 : 0.0) - a.eta * acc.re, -a.eta * acc.im);
     }
-    qy[(size_t)b * rr + e] = qv;
-    gyp[(size_t)b * rr + e] = gp[e];
+    a.qy[(size_t)b * rr + e] = qv;
+    a.gyp[(size_t)b * rr + e] = gp[e];
   }
-  if (tid == 0) qy_zero[b] = qyz ? 1 : 0;
+  if (tid == 0) a.qy_zero[b] = qyz ? 1 : 0;
 }
