@@ -29,29 +29,6 @@ __device__ __forceinline__ v4d mfma4d(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Two consecutive complex entries of W~ (j, j + 1) as four floats; entries past the end read 0.
-template <bool MIXED>
-__device__ __forceinline__ float4 ld_wt2(const void* wt, size_t idx, int valid) {
-  // both loads unconditional (as ld_or): the first from W~[0] when valid == 0, the second
-  // repeats the first when valid < 2
-  const size_t i0 = valid > 0 ? idx : 0, i1 = valid > 1 ? idx + 1 : i0;
-  float2 a, c;
-  if constexpr (MIXED) {
-    const uint32_t* w = (const uint32_t*)wt;
-    const uint32_t u0 = w[i0], u1 = w[i1];
-    a = unpack_bf16x2(u0);
-    c = unpack_bf16x2(u1);
-  } else {
-    const float2* w = (const float2*)wt;
-    a = w[i0];
-    c = w[i1];
-  }
-  const float2 z = make_float2(0.f, 0.f);
-  if (valid < 1) a = z;
-  if (valid < 2) c = z;
-  return make_float4(a.x, a.y, c.x, c.y);
-}
-
 // ---------------------------------------------------------------- Z~ = X~ Y~
 // Real form: Z'[i][2j + c] = sum_kk X'[i][kk] Y'[kk][2j + c] with kk = 2s + d,
 // X'[i][2s + d] = (re, im)_d X~(i, s) and Y' carrying the signs of the complex product:
@@ -182,9 +159,9 @@ __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, cons
                                                const cd* __restrict__ qy, const int* __restrict__ qy_zero,
                                                float2* __restrict__ rhs, int n1, int n2, int r, int nb,
                                                double eta, double rho1, int mixed, int raw_a) {
-  __shared__ __align__(16) float2 ysh[TCTF_RMAX * AG_COLS];   // [s][j] of the column chunk (32 KB)
-  __shared__ __align__(16) float2 ash[AG_ROWS * TCTF_RMAX];   // A rows, then the results (16 KB)
-  __shared__ __align__(16) cd gs[TCTF_RMAX * TCTF_RMAX];      // G_Y^+ (16 KB)
+  __shared__ __align__(16) float2 ysh[RM * AG_COLS];   // [s][j] of the column chunk
+  __shared__ __align__(16) float2 ash[AG_ROWS * RM];   // A rows, then the results
+  __shared__ __align__(16) cd gs[RM * RM];             // G_Y^+
   const int i0 = blockIdx.x * AG_ROWS, b = blockIdx.y, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
   const int row = i0 + 16 * w + m;
@@ -197,14 +174,31 @@ __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, cons
   for (int j0 = 0; j0 < n2; j0 += AG_COLS) {
     const int nc = min(AG_COLS, n2 - j0), ngroups = (nc + 7) / 8;
     // W~ operands of this pass: group g covers columns j0 + 8 g .. + 7; this lane takes 2
-    // (the storage branch outside the unrolled loop, so that no load waits at a join)
+    // All loads unconditional from one base (row clamped into range, immediate offsets; the
+    // W~ buffer has AG_COLS elements of slack past its end) and masked afterwards; the
+    // storage branch sits outside the unrolled loop, so that no load waits at a join.
     float4 wa[AG_COLS / 8];
+    const size_t wbase = ((size_t)min(row, n1 - 1) * nb + b) * n2 + j0 + 2 * q;
     auto load_wa = [&](auto mixed_tag) {
+      float2 lo[AG_COLS / 8], hi[AG_COLS / 8];
+#pragma unroll
+      for (int g = 0; g < AG_COLS / 8; ++g) {
+        if constexpr (decltype(mixed_tag)::value) {
+          const uint32_t* w = (const uint32_t*)wt + wbase;
+          lo[g] = unpack_bf16x2(w[8 * g]);
+          hi[g] = unpack_bf16x2(w[8 * g + 1]);
+        } else {
+          const float2* w = (const float2*)wt + wbase;
+          lo[g] = w[8 * g];
+          hi[g] = w[8 * g + 1];
+        }
+      }
 #pragma unroll
       for (int g = 0; g < AG_COLS / 8; ++g) {
         const int jj = 8 * g + 2 * q;
         const int valid = (g < ngroups && row < n1) ? min(2, nc - jj) : 0;
-        wa[g] = ld_wt2<decltype(mixed_tag)::value>(wt, ((size_t)row * nb + b) * n2 + j0 + jj, valid);
+        const float2 z = make_float2(0.f, 0.f), a = valid > 0 ? lo[g] : z, c = valid > 1 ? hi[g] : z;
+        wa[g] = make_float4(a.x, a.y, c.x, c.y);
       }
     };
     if (mixed) load_wa(std::true_type{});
@@ -332,71 +326,72 @@ void launch_agemm(const Plan& p, int raw_a) {
 #undef TCTF_AGEMM
 }
 
-// Outputs of gramx_block, per frequency b ([nb][r][r] FP64 complex unless noted).
+// Output of gramx_block.
 struct GramOut {
-  cd* gxm;       // G_X
-  cd* dmat;      // (H X~)^*(H X~)
-  cd* gxp;       // G_X^+
-  cd* qx;        // I - eta G_X^+ G_X (not written when it is exactly 0)
-  int* qx_zero;  // [nb] 1 when I - eta P_X = 0
-  double rho1, eta;
-  int force_eigen;
+  cd* gxpart;   // [nb][ngs][2][r][r] the row groups' partial X~^* X~ and (H X~)^*(H X~)
+  int ngx;      // row groups per frequency
+  int ngs;      // group stride of gxpart (>= ngx)
 };
 
-// Rows per staged group of gramx_block (plus the next row): 256 when the one sweep's
-// partials can take the staging area afterwards, 64 at r > 16.
+// Rows per group of gramx_block (plus the next row): 256, and 64 at r > 16 where the two
+// sweeps need the partials beside the staging area.
 #define GX_ROWS(RM) ((RM) <= 16 ? 256 : 64)
 
-// LDS bytes of gramx_block at rank r <= RM: the staged rows and the complex Gram partials,
-// later G_X with the pseudo-inverse scratch.
+// LDS bytes of gramx_block at rank r <= RM: the staged rows and the complex Gram partials.
 static inline size_t gramx_lds_bytes(int r, int rm) {
   const int ks = rm == 8 ? 4 : 1;
   const size_t sb = (size_t)2 * rm * (GX_ROWS(rm) + 4) * sizeof(float);
   const size_t pb = (size_t)ks * 2 * r * r * sizeof(cd);
-  const size_t a = rm <= 16 ? (sb > pb ? sb : pb) : sb + pb;
-  return a > pinvy_lds_bytes(r) ? a : pinvy_lds_bytes(r);
+  return rm <= 16 ? (sb > pb ? sb : pb) : sb + pb;
 }
 
-// Frequency b, by a whole block: the FP64 Grams C = X'^T X' and the same for the row
-// differences X'(i + 1) - X'(i) over all n1 rows, as 16 x 16 x 4 FP64 matrix-core tiles.
-// Rows arrive in groups of GR (plus the next row), staged column by column (X'^T, columns
-// past 2r zero), the next group's loads in flight while the current one is multiplied.
-// Within 16 rows the K order is permuted: lane (m, q) feeds rows 4 q .. 4 q + 3 of the 16,
-// so one 16-byte LDS read (and one float of the following row) serves four steps.  Full
-// groups need no masks; the last group masks rows past n1 (and the difference at the last
-// row).  At r <= 8 the four wavefronts share the one tile and split the rows; at r > 16 each
-// wavefront takes its four tiles in two sweeps over the rows.  The lanes holding C[2s][2t]
+// Row group g (rows g GR .. g GR + GR - 1) of frequency b, by a whole block: the group's
+// FP64 Grams C = X'^T X' and the same for the row differences X'(i + 1) - X'(i) (the
+// difference at row i belongs to the group of row i), as 16 x 16 x 4 FP64 matrix-core
+// tiles.  The rows (and the next one) are staged column by column (X'^T; columns past 2r and
+// rows past n1 zero).  Within 16 rows the K order is permuted: lane (m, q) feeds rows
+// 4 q .. 4 q + 3 of the 16, so one 16-byte LDS read (and one float of the following row)
+// serves four steps.  A full group needs no masks; the last group masks the difference at
+// the last row.  At r <= 8 the four wavefronts share the one tile and split the rows; at
+// r > 16 each wavefront takes its four tiles in two sweeps.  The lanes holding C[2s][2t]
 // gather the 2 x 2 real block by shuffles and form X~^* X~ (s, t) = (C[2s][2t] +
-// C[2s+1][2t+1], C[2s][2t+1] - C[2s+1][2t]), likewise (H X~)^*(H X~); then
-// G_X = X~^* X~ + rho1 (H X~)^*(H X~), its pseudo-inverse (Lemma SVPMPI, pinv_herm) and
-// I - eta P_X.
+// C[2s+1][2t+1], C[2s][2t+1] - C[2s+1][2t]), likewise (H X~)^*(H X~); the group's two
+// complex partials go to gxpart (the Y-step sums them in group order).
 template <int RM>
-__device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1, int r, const GramOut& go,
+__device__ inline void gramx_block(int b, int g, const float2* __restrict__ xt, int n1, int r, const GramOut& go,
                                    unsigned char* sm) {
   constexpr int MT = RM / 8, NT = MT * MT;         // 16 x 16 tiles of the real Gram
   constexpr int KS = NT >= 4 ? 1 : 4 / NT;         // wavefronts sharing a tile (row split)
   constexpr int TPW = NT >= 4 ? NT / 4 : 1;        // tiles per wavefront
-  constexpr int TPS = TPW < 2 ? TPW : 2;           // tiles per sweep over the rows
+  constexpr int TPS = TPW < 2 ? TPW : 2;           // tiles per sweep
   constexpr int NSW = TPW / TPS;                   // sweeps
   constexpr int GR = GX_ROWS(RM);                  // rows per group
   constexpr int LD = GR + 4;                       // LDS stride of a staged column (floats)
   constexpr int PER = ((GR + 1) * RM + 255) / 256; // staged elements per thread (GR + 1 rows)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
   const int rr = r * r, kp = KS > 1 ? w : 0;
+  const int i0 = g * GR, nrows = min(GR, n1 - i0);
+  const bool full = i0 + GR < n1;   // GR rows and the next one: no masks
   float* xs = (float*)sm;   // [2 RM][LD]: X'^T, column 2 s + d of X' is row 2 s + d here
   // [KS][2][rr]: after the staging area, or in it when one sweep leaves it free
   cd* part = (cd*)(sm + (NSW > 1 ? (size_t)2 * RM * LD * sizeof(float) : 0));
-  // element e of a group: column s = e / (GR + 1), row h = e % (GR + 1); rows and columns
-  // past the matrix load as zeros
-  float2 pf[PER];
-  auto load_group = [&](int i0) {
+  {  // element e: column s = e / (GR + 1), row h = e % (GR + 1); past the matrix: zeros
+    float2 pf[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + 256 * u, s = e / (GR + 1), h = e % (GR + 1);
       pf[u] = ld_or(xt, ((size_t)b * r + s) * n1 + i0 + h, s < r && i0 + h < n1, make_float2(0.f, 0.f));
     }
-  };
-  load_group(0);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, s = e / (GR + 1), h = e % (GR + 1);
+      if (s < RM) {
+        xs[(2 * s) * LD + h] = pf[u].x;
+        xs[(2 * s + 1) * LD + h] = pf[u].y;
+      }
+    }
+  }
+  __syncthreads();
 #pragma unroll
   for (int sw = 0; sw < NSW; ++sw) {
     v4d acs[TPS], acd[TPS];
@@ -405,47 +400,31 @@ __device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1,
       acs[u] = v4d{0.0, 0.0, 0.0, 0.0};
       acd[u] = v4d{0.0, 0.0, 0.0, 0.0};
     }
-    for (int i0 = 0; i0 < n1; i0 += GR) {
-      const int nrows = min(GR, n1 - i0);
-      __syncthreads();   // the previous rows are consumed
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int e = tid + 256 * u, s = e / (GR + 1), h = e % (GR + 1);
-        if (s < RM) {
-          xs[(2 * s) * LD + h] = pf[u].x;
-          xs[(2 * s + 1) * LD + h] = pf[u].y;
-        }
-      }
-      __syncthreads();
-      if (i0 + GR < n1) load_group(i0 + GR);
-      else if (sw + 1 < NSW) load_group(0);
-      const bool full = i0 + GR < n1;   // GR rows and the next one, no masks
+    for (int u = 0; u < TPS; ++u) {
+      const int tile = KS > 1 ? 0 : w + 4 * (sw * TPS + u);
+      const float* pa = xs + (16 * (tile / MT) + m) * LD;   // column 2 s + d of X'
+      const float* pb = xs + (16 * (tile % MT) + m) * LD;
+      auto step16 = [&](int jb, auto masked) {
+        const int h0 = 16 * jb + 4 * q;
+        const float4 a4 = *(const float4*)(pa + h0), b4 = *(const float4*)(pb + h0);
+        const double av[5] = {a4.x, a4.y, a4.z, a4.w, pa[h0 + 4]};
+        const double bv[5] = {b4.x, b4.y, b4.z, b4.w, pb[h0 + 4]};
 #pragma unroll
-      for (int u = 0; u < TPS; ++u) {
-        const int tile = KS > 1 ? 0 : w + 4 * (sw * TPS + u);
-        const float* pa = xs + (16 * (tile / MT) + m) * LD;   // column 2 s + d of X'
-        const float* pb = xs + (16 * (tile % MT) + m) * LD;
-        auto step16 = [&](int jb, auto masked) {
-          const int h0 = 16 * jb + 4 * q;
-          const float4 a4 = *(const float4*)(pa + h0), b4 = *(const float4*)(pb + h0);
-          const double av[5] = {a4.x, a4.y, a4.z, a4.w, pa[h0 + 4]};
-          const double bv[5] = {b4.x, b4.y, b4.z, b4.w, pb[h0 + 4]};
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) {
-            double a1 = av[jj + 1] - av[jj], b1 = bv[jj + 1] - bv[jj];
-            if constexpr (decltype(masked)::value) {   // the row past n1 is staged as zero
-              if (i0 + h0 + jj + 1 >= n1) a1 = b1 = 0.0;
-            }
-            acs[u] = mfma4d(av[jj], bv[jj], acs[u]);
-            acd[u] = mfma4d(a1, b1, acd[u]);
+        for (int jj = 0; jj < 4; ++jj) {
+          double a1 = av[jj + 1] - av[jj], b1 = bv[jj + 1] - bv[jj];
+          if constexpr (decltype(masked)::value) {   // no difference at the last row
+            if (i0 + h0 + jj + 1 >= n1) a1 = b1 = 0.0;
           }
-        };
-        if (full) {
-#pragma unroll 2
-          for (int jb = kp; jb < GR / 16; jb += KS) step16(jb, std::false_type{});
-        } else {
-          for (int jb = kp; 16 * jb < nrows; jb += KS) step16(jb, std::true_type{});
+          acs[u] = mfma4d(av[jj], bv[jj], acs[u]);
+          acd[u] = mfma4d(a1, b1, acd[u]);
         }
+      };
+      if (full) {
+#pragma unroll 2
+        for (int jb = kp; jb < GR / 16; jb += KS) step16(jb, std::false_type{});
+      } else {
+        for (int jb = kp; 16 * jb < nrows; jb += KS) step16(jb, std::true_type{});
       }
     }
     if (NSW == 1) __syncthreads();   // the partials take the staging area
@@ -470,52 +449,18 @@ __device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1,
     }
   }
   __syncthreads();
-  constexpr int GPT = (RM * RM + 255) / 256;   // G_X entries per thread
-  cd gv[GPT];
-#pragma unroll
-  for (int k = 0; k < GPT; ++k) {
-    const int e = tid + 256 * k;
-    gv[k] = cd_make(0.0, 0.0);
-    if (e < rr) {
-      cd sv = part[e], dv = part[rr + e];
-#pragma unroll
-      for (int j = 1; j < KS; ++j) {   // the row parts, in a fixed order
-        sv = cd_add(sv, part[2 * j * rr + e]);
-        dv = cd_add(dv, part[(2 * j + 1) * rr + e]);
-      }
-      gv[k] = cd_add(sv, cd_scale(dv, go.rho1));
-      go.gxm[(size_t)b * rr + e] = gv[k];
-      go.dmat[(size_t)b * rr + e] = dv;
-    }
-  }
-  __syncthreads();   // the partials are read; G_X and the pinv scratch take their place
-  cd* gx = (cd*)sm;
-  cd* gp = gx + rr;
-  PinvScratch ps;
-  ps.work = gp + rr;
-  ps.vec = ps.work + rr;
-  ps.colk = ps.vec + rr;
-  ps.rowk = ps.colk + r;
-  ps.rot = (double*)(ps.rowk + r);
-  ps.red = ps.rot + 96;
-#pragma unroll
-  for (int k = 0; k < GPT; ++k) {
-    const int e = tid + 256 * k;
-    if (e < rr) gx[e] = gv[k];
-  }
-  __syncthreads();
-  const int full = pinv_herm(gx, gp, r, go.force_eigen, ps);
-  const bool qzero = full && go.eta == 1.0;
+  // this group's partials (the row parts summed in a fixed order)
+  cd* gpart = go.gxpart + ((size_t)b * go.ngs + g) * 2 * rr;
   for (int e = tid; e < rr; e += 256) {
-    go.gxp[(size_t)b * rr + e] = gp[e];
-    if (!qzero) {   // q = I - eta G_X^+ G_X
-      const int s = e / r, t = e % r;
-      cd acc = cd_make(0.0, 0.0);
-      for (int u = 0; u < r; ++u) cd_fma(acc, gp[s * r + u], gx[u * r + t]);
-      go.qx[(size_t)b * rr + e] = cd_make((s == t ? 1.0 : 0.0) - go.eta * acc.re, -go.eta * acc.im);
+    cd sv = part[e], dv = part[rr + e];
+#pragma unroll
+    for (int j = 1; j < KS; ++j) {
+      sv = cd_add(sv, part[2 * j * rr + e]);
+      dv = cd_add(dv, part[(2 * j + 1) * rr + e]);
     }
+    gpart[e] = sv;
+    gpart[rr + e] = dv;
   }
-  if (tid == 0) go.qx_zero[b] = qzero ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- X~^* W~, and G_X with its inverse
@@ -526,10 +471,9 @@ __device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1,
 // of BG_COLS columns, its whole W~ slab are staged in LDS with every load of a thread
 // issued at once; each wavefront owns a quarter of the 16-column tiles of a pass.  After
 // every 16 rows the FP32 tile sums are added into FP64 accumulators.
-// At r <= 16 the first nb blocks of the launch instead form, for frequency blockIdx.x, the
-// whole Gram G_X = X~^* X~ + rho1 (H X~)^*(H X~) in FP64 on the matrix cores, its
-// pseudo-inverse and I - eta P_X (gramx_block): the Y-step needs them, and they run beside
-// the products; at r > 16 k_gramx does this work in a launch of its own.
+// At r <= 16 the first nb ngx blocks of the launch instead form the row-group partials of
+// X~^* X~ and (H X~)^*(H X~) in FP64 on the matrix cores (gramx_block), beside the products;
+// at r > 16 k_gramx does this work in a launch of its own.
 #define BG_COLS 64                  // complex columns per pass
 #define BG_MAXROWS 64               // rows per chunk at most
 #define BG_WLD (2 * BG_COLS + 16)   // LDS row stride of the staged W~ slab (floats)
@@ -539,10 +483,10 @@ k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, float2* __re
         int n2, int r, int nb, int nchunk, int chunk, int mixed) {
   extern __shared__ __align__(16) float smb[];
   constexpr bool GRAM = RM <= 16;   // at r > 16 the registers of both paths would not fit twice
-  const int ng = GRAM ? nb : 0;     // G_X blocks at the front of the grid
+  const int ng = GRAM ? nb * go.ngx : 0;   // G_X row-group blocks at the front of the grid
   if constexpr (GRAM) {
-    if ((int)blockIdx.x < nb) {
-      gramx_block<RM>(blockIdx.x, xt, n1, r, go, (unsigned char*)smb);
+    if ((int)blockIdx.x < ng) {
+      gramx_block<RM>(blockIdx.x / go.ngx, blockIdx.x % go.ngx, xt, n1, r, go, (unsigned char*)smb);
       return;
     }
   }
@@ -666,13 +610,15 @@ k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, float2* __re
   }
 }
 
-// G_X alone, one block per frequency (r > 16: beside the products it would cost them
+// The row-group partials of G_X alone (r > 16: beside the products they would cost them
 // registers).
 template <int RM>
 __global__ void __launch_bounds__(256) k_gramx(const float2* __restrict__ xt, GramOut go, int n1, int r) {
   extern __shared__ __align__(16) unsigned char smg[];
-  gramx_block<RM>(blockIdx.x, xt, n1, r, go, smg);
+  gramx_block<RM>(blockIdx.x / go.ngx, blockIdx.x % go.ngx, xt, n1, r, go, smg);
 }
+
+int gramx_groups(int n1, int r) { return (n1 + GX_ROWS(r <= 8 ? 8 : (r <= 16 ? 16 : 32)) - 1) / GX_ROWS(r <= 8 ? 8 : (r <= 16 ? 16 : 32)); }
 
 size_t bgemm_lds_bytes(int r, int chunk) {
   const int rm = r <= 8 ? 8 : (r <= 16 ? 16 : 32);
@@ -693,17 +639,12 @@ void bgemm_set_attr(size_t lds) {
 
 void launch_bgemm(const Plan& p) {
   const bool fused = p.r <= 16;
-  const int grid = (fused ? p.nb : 0) + p.nchunk * p.nb;   // G_X blocks first, then (chunk, frequency)
+  const int grid = (fused ? p.nb * p.ngx : 0) + p.nchunk * p.nb;   // G_X groups first, then (chunk, frequency)
   const size_t lds = bgemm_lds_bytes(p.r, p.chunk);
   GramOut go;
-  go.gxm = p.gxm;
-  go.dmat = p.dmat;
-  go.gxp = p.gxp;
-  go.qx = p.qx;
-  go.qx_zero = p.qx_zero;
-  go.rho1 = p.rho1;
-  go.eta = p.eta;
-  go.force_eigen = p.force_eigen;
+  go.gxpart = p.gxpart;
+  go.ngx = p.ngx;
+  go.ngs = p.ngs;
 #define TCTF_BGEMM(RM)                                                                                  \
   k_bgemm<RM><<<grid, 256, lds, p.stream>>>(p.wt, p.xt, p.bpart, go, p.n1, p.n2, p.r, p.nb, p.nchunk, \
                                             p.chunk, p.mixed)
@@ -712,7 +653,7 @@ void launch_bgemm(const Plan& p) {
   } else if (p.r <= 16) {
     TCTF_BGEMM(16);
   } else {
-    k_gramx<32><<<p.nb, 256, lds, p.stream>>>(p.xt, go, p.n1, p.r);
+    k_gramx<32><<<p.nb * p.ngx, 256, lds, p.stream>>>(p.xt, go, p.n1, p.r);
     TCTF_BGEMM(32);
   }
 #undef TCTF_BGEMM

@@ -169,18 +169,17 @@ void launch_hsolve(const Plan& p) {
   k_hsolve<<<p.nb * p.r * 2, 64, lds, p.stream>>>(p.rhs, p.htab, p.xt, p.n1, p.r, p.n3);
 }
 
-// Dynamic LDS layout of k_ystep (r x r FP64 complex matrices, then the column block of
-// cw columns with an odd row stride cw | 1, so that the rows of one column fall in
-// different LDS banks).
-#define YS_CP 8   // chunk partials of X~^* W~ loaded together
+// Dynamic LDS layout of k_ystep: the pseudo-inverse area (G_X, G_X^+ and the pinv_herm
+// scratch, as pinvy_lds_bytes), q = I - eta P_X, then the column block of cw columns with an
+// odd row stride cw | 1, so that the rows of one column fall in different LDS banks.
 struct YLayout {
-  size_t gp, q, bsum, yold, ynew, total;
+  size_t gx, q, bsum, yold, ynew, total;
 };
 __host__ __device__ inline YLayout ystep_layout(int r, int cw) {
   YLayout L;
   const size_t m = (size_t)r * r * sizeof(cd), ld = (size_t)(cw | 1);
   size_t o = 0;
-  L.gp = o; o += m;
+  L.gx = o; o += pinvy_lds_bytes(r);
   L.q = o; o += m;
   L.bsum = o; o += (size_t)r * ld * sizeof(cd);       // columns of X~^* W~ (FP64)
   L.yold = o; o += (size_t)r * ld * sizeof(float2);   // the same columns of the old Y~
@@ -189,92 +188,167 @@ __host__ __device__ inline YLayout ystep_layout(int r, int cw) {
   return L;
 }
 
+#define YS_GXG(RM) ((RM) <= 16 ? 4 : 1)   // row groups of the G_X partials the Y-step loads up front
+
 // Column blocks of the Y-step: enough blocks to cover the compute units, at least 8 columns
-// each, at most 1024 / r (four elements per thread).
+// each, at most 512 / r (two elements per thread).
+int ystep_gx_groups(int r) { return YS_GXG(r <= 16 ? 16 : 32); }
+
 void ystep_split(int n2, int r, int nb, int* ny, int* cw) {
   const int want = (256 + nb - 1) / nb;
   int c = (n2 + want - 1) / want;
   if (c < 8) c = 8;
-  if (c > 1024 / r) c = 1024 / r;
+  if (c > 512 / r) c = 512 / r;
   if (c > n2) c = n2;
   *cw = c;
   *ny = (n2 + c - 1) / c;
 }
 
-// Block (column block jb, frequency b), 256 threads; G_X^+ and I - eta P_X come from the
-// X~^* W~ launch (gramx_block).  The chunk partials of X~^* W~ for the block's columns and the
-// old columns are loaded together (independent loads, summed in a fixed order), the new
-// columns Y~ <- (I - eta P_X) Y~ + eta G_X^+ X~^* W~ (eq. (updataXYW1)) are formed in FP64 and
-// stored in FP32, and the block's FP64 partial of G_Y = Y~ Y~^* is formed from the stored
-// values.  init: only the partial of G_Y.
+// Block (column block jb, frequency b), 256 threads, r <= RM.  The loads are issued in the
+// order they are needed, all before the first use: the row-group partials of X~^* X~ and
+// (H X~)^*(H X~), then the old columns and the first YS_CP1 chunk partials of X~^* W~ for
+// the block's columns.  While the latter are in flight the block sums the former (group
+// order) into G_X = X~^* H_rho1 X~ and forms G_X^+ (Lemma SVPMPI, pinv_herm) and
+// I - eta P_X; block 0 of the frequency also stores G_X and (H X~)^*(H X~).  Then the chunk
+// partials are summed (fixed order) and Y~ <- (I - eta P_X) Y~ + eta G_X^+ X~^* W~
+// (eq. (updataXYW1)) is formed on the block's columns in FP64 and stored in FP32, and the
+// block's FP64 partial of G_Y = Y~ Y~^* is formed from the stored values.  init: only
+// (H X~)^*(H X~) and the partial of G_Y.
+#define YS_CP1 12   // chunk partials of X~^* W~ in the first batch of loads
+#define YS_CP 8     // and in each later batch
+template <int RM>
 __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const float2* __restrict__ bpart,
-                                               const cd* __restrict__ gxp, const cd* __restrict__ qx,
-                                               const int* __restrict__ qx_zero, cd* __restrict__ gyq, int n2,
-                                               int r, int n3, int nchunk, int cw, int ny, double eta, int init) {
+                                               const cd* __restrict__ gxpart, int ngx, int ngs, cd* __restrict__ gxm,
+                                               cd* __restrict__ dmat, cd* __restrict__ gyq, int n2, int r, int n3,
+                                               int nchunk, int cw, int ny, double eta, double rho1,
+                                               int force_eigen, int init) {
+  constexpr int GPT = (RM * RM + 255) / 256;   // G_X entries per thread
+  constexpr int GXG = YS_GXG(RM);              // row groups loaded up front
   extern __shared__ __align__(16) unsigned char sm[];
   const YLayout L = ystep_layout(r, cw);
-  cd* gp = (cd*)(sm + L.gp);
+  const int jb = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, rr = r * r;
+  cd* gx = (cd*)(sm + L.gx);
+  cd* gp = gx + rr;
+  PinvScratch ps;
+  ps.work = gp + rr;
+  ps.vec = ps.work + rr;
+  ps.colk = ps.vec + rr;
+  ps.rowk = ps.colk + r;
+  ps.rot = (double*)(ps.rowk + r);
+  ps.red = ps.rot + 96;
   cd* q = (cd*)(sm + L.q);
   cd* bsum = (cd*)(sm + L.bsum);
   float2* yold = (float2*)(sm + L.yold);
   float2* ynew = (float2*)(sm + L.ynew);
-  const int jb = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, rr = r * r;
   const int j0 = jb * cw, nj = min(cw, n2 - j0), nel = r * nj, ld = cw | 1;
   const bool real_bin = bin_is_real(b, n3);
-  const bool qzero = init || qx_zero[b] != 0;
   const float2 z2 = make_float2(0.f, 0.f);
   const cd zc = cd_make(0.0, 0.0);
+  const cd* p0 = gxpart + (size_t)b * ngs * 2 * rr;
 
-  // every load of the block issued before any use: old columns, chunk partials (YS_CP at a
-  // time), G_X^+ and q
-  float2 y[4];
-  cd acc[4];
-  size_t base[4];
+  // 1. the first GXG row groups of the G_X partials, loaded without masks: the buffer holds
+  // at least GXG zero-filled groups per frequency and slack past its end (values past rr
+  // are dropped below)
+  cd sp[GPT][GXG], dp[GPT][GXG];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int k = 0; k < GPT; ++k)
+#pragma unroll
+    for (int g = 0; g < GXG; ++g) {
+      const int e = tid + 256 * k;
+      sp[k][g] = p0[(size_t)g * 2 * rr + e];
+      dp[k][g] = p0[(size_t)g * 2 * rr + rr + e];
+    }
+  // 2. the old columns and the first chunk partials of X~^* W~ (two elements per thread)
+  float2 y[2], v[2][YS_CP1];
+  size_t base[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
     const int e = tid + 256 * u, t = e / nj, jj = e % nj;
     base[u] = ((size_t)b * nchunk * r + t) * n2 + j0 + jj;
     y[u] = ld_or(yt, ((size_t)b * r + t) * n2 + j0 + jj, e < nel, z2);
-    acc[u] = zc;
-  }
-  cd g4[4], q4[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = tid + 256 * u;
-    g4[u] = ld_or(gxp, (size_t)b * rr + e, !init && e < rr, zc);
-    q4[u] = ld_or(qx, (size_t)b * rr + e, !qzero && e < rr, zc);
+    for (int k = 0; k < YS_CP1; ++k)
+      v[u][k] = ld_or(bpart, base[u] + (size_t)k * r * n2, !init && e < nel && k < nchunk, z2);
+  }
+  // 3. G_X (group order; groups past GXG, if any, read now).  The sums are formed by every
+  // thread and only the stores are conditional, so that the loads above are not moved into
+  // a branch past the ones that follow them.
+#pragma unroll
+  for (int k = 0; k < GPT; ++k) {
+    const int e = tid + 256 * k;
+    cd sv = sp[k][0], dv = dp[k][0];
+#pragma unroll
+    for (int g = 1; g < GXG; ++g) {
+      sv = cd_add(sv, sp[k][g]);
+      dv = cd_add(dv, dp[k][g]);
+    }
+    for (int g = GXG; g < ngx; ++g) {
+      sv = cd_add(sv, ld_or(p0, (size_t)g * 2 * rr + e, e < rr, zc));
+      dv = cd_add(dv, ld_or(p0, (size_t)g * 2 * rr + rr + e, e < rr, zc));
+    }
+    const cd gv = cd_add(sv, cd_scale(dv, rho1));
+    if (e < rr) {
+      gx[e] = gv;
+      if (jb == 0) {
+        gxm[(size_t)b * rr + e] = gv;
+        dmat[(size_t)b * rr + e] = dv;
+      }
+    }
+  }
+  __syncthreads();
+  // 4. G_X^+ and q while the column loads are in flight
+  bool qzero = true;
+  if (!init) {
+    const int full = pinv_herm(gx, gp, r, force_eigen, ps);
+    qzero = full && eta == 1.0;
+    if (!qzero) {   // q = I - eta G_X^+ G_X
+      for (int e = tid; e < rr; e += 256) {
+        const int s = e / r, t = e % r;
+        cd a = zc;
+        for (int u = 0; u < r; ++u) cd_fma(a, gp[s * r + u], gx[u * r + t]);
+        q[e] = cd_make((s == t ? 1.0 : 0.0) - eta * a.re, -eta * a.im);
+      }
+    }
+  }
+  // 5. the chunk sums (fixed order), later chunks in batches
+  cd acc[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    acc[u] = zc;
+#pragma unroll
+    for (int k = 0; k < YS_CP1; ++k) {
+      acc[u].re += v[u][k].x;
+      acc[u].im += v[u][k].y;
+    }
   }
   if (!init) {
-    for (int c0 = 0; c0 < nchunk; c0 += YS_CP) {
-      float2 v[4][YS_CP];
+    for (int c0 = YS_CP1; c0 < nchunk; c0 += YS_CP) {
+      float2 w[2][YS_CP];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int k = 0; k < YS_CP; ++k)
-          v[u][k] = ld_or(bpart, base[u] + (size_t)(c0 + k) * r * n2, tid + 256 * u < nel && c0 + k < nchunk, z2);
+          w[u][k] = ld_or(bpart, base[u] + (size_t)(c0 + k) * r * n2, tid + 256 * u < nel && c0 + k < nchunk, z2);
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int k = 0; k < YS_CP; ++k) {
-          acc[u].re += v[u][k].x;
-          acc[u].im += v[u][k].y;
+          acc[u].re += w[u][k].x;
+          acc[u].im += w[u][k].y;
         }
     }
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < 2; ++u) {
     const int e = tid + 256 * u;
     if (e < nel) {
       const int t = e / nj, jj = e % nj;
       yold[t * ld + jj] = y[u];
       bsum[t * ld + jj] = acc[u];
     }
-    if (e < rr) {
-      gp[e] = g4[u];
-      q[e] = q4[u];
-    }
   }
   __syncthreads();
+  // 6. the new columns, then the partial of G_Y from the stored values
   if (!init) {
     for (int e = tid; e < nel; e += 256) {
       const int s = e / nj, jj = e % nj;
@@ -289,21 +363,20 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const fl
         }
       }
       a1 = cd_add(a1, cd_scale(a2, eta));
-      const float2 v = make_float2((float)a1.re, real_bin ? 0.0f : (float)a1.im);
-      ynew[s * ld + jj] = v;
-      yt[((size_t)b * r + s) * n2 + j0 + jj] = v;
+      const float2 o = make_float2((float)a1.re, real_bin ? 0.0f : (float)a1.im);
+      ynew[s * ld + jj] = o;
+      yt[((size_t)b * r + s) * n2 + j0 + jj] = o;
     }
     __syncthreads();
   }
-  // partial G_Y(s, t) = sum over the block's columns of Y~(s, j) conj(Y~(t, j)), stored values
   const float2* yb = init ? yold : ynew;
   for (int e = tid; e < rr; e += 256) {
     const int s = e / r, t = e % r;
     cd g = zc;
 #pragma unroll 4
     for (int jj = 0; jj < nj; ++jj) {
-      const float2 u = yb[s * ld + jj], v = yb[t * ld + jj];
-      cd_fma(g, cd_make(u.x, u.y), cd_make(v.x, -v.y));
+      const float2 a = yb[s * ld + jj], c = yb[t * ld + jj];
+      cd_fma(g, cd_make(a.x, a.y), cd_make(c.x, -c.y));
     }
     gyq[((size_t)b * ny + jb) * rr + e] = g;
   }
@@ -329,14 +402,23 @@ void launch_pinvy(const Plan& p, hipStream_t stream) {
 size_t ystep_lds_bytes(int r, int cw) { return ystep_layout(r, cw).total; }
 
 void ystep_set_attr(size_t lds) {
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_ystep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 65536) {
+    (void)hipFuncSetAttribute((const void*)k_ystep<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_ystep<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_ystep<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
 }
 
 void launch_ystep(const Plan& p, int init) {
   const size_t lds = ystep_layout(p.r, p.ycw).total;
-  k_ystep<<<dim3(p.ny, p.nb), 256, lds, p.stream>>>(p.yt, p.bpart, p.gxp, p.qx, p.qx_zero, p.gym, p.n2, p.r, p.n3,
-                                                   p.nchunk, p.ycw, p.ny, p.eta, init);
+  const dim3 grid(p.ny, p.nb);
+#define TCTF_YSTEP(RM)                                                                                        \
+  k_ystep<RM><<<grid, 256, lds, p.stream>>>(p.yt, p.bpart, p.gxpart, p.ngx, p.ngs, p.gxm, p.dmat, p.gym, p.n2, \
+                                            p.r, p.n3, p.nchunk, p.ycw, p.ny, p.eta, p.rho1, p.force_eigen, init)
+  if (p.r <= 8) TCTF_YSTEP(8);
+  else if (p.r <= 16) TCTF_YSTEP(16);
+  else TCTF_YSTEP(32);
+#undef TCTF_YSTEP
 }
 
 }  // namespace tctf

@@ -43,6 +43,7 @@ def test_smallest_workload_50_iterations():
     (130, 20, 16, 8, 0.6),    # several 64-row chunks in the n1 reduction
     (48, 40, 6, 20, 0.7),     # r > 16: the largest rank bucket of the products and pivots
     (1100, 9, 4, 2, 0.5),     # n1 > 1024: the column-in-LDS H solve
+    (300, 12, 6, 3, 0.4),     # n1 past one round of compute units, two row groups of G_X
 ])
 def test_ragged_shapes(n1, n2, n3, r, p):
     d = make_inputs(n1, n2, n3, r, p=p, seed=n1 + n2 + n3, weekly=True, sigma_od=1.0, noise=0.02)
@@ -200,3 +201,12 @@ def test_run_until_termination_stops_where_the_oracle_does():
     c2 = Completion(to_dev(d["G"]), to_dev(d["omega"]), 3, X0=to_dev(d["X0"]), Y0=to_dev(d["Y0"]), eps=eps)
     n2, conv2 = c2.run(n_stop, check_every=4)   # stops at the budget before the test holds
     assert not conv2 and n2 == n_stop
+
+
+def test_two_row_groups_through_graph_replays():
+    """n1 = 300 (two row groups of the G_X Gram) over 23 iterations: two graph replays of 10
+    iterations and eager ones, against the oracle."""
+    d = make_inputs(300, 14, 5, 3, p=0.4, seed=3005, weekly=True, sigma_od=1.0, noise=0.02)
+    g = gpu_run(d, 3, 23)
+    st, info = oracle_run(d, 3, 23, history=False)
+    _compare(g, st, info, label="300x14x5 r3, 23 iterations")
