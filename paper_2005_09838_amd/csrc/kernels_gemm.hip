@@ -153,12 +153,12 @@ void launch_zgemm(const Plan& p, int with_pinv) {
 // I - eta P_Y is not exactly 0).
 #define AG_ROWS 64
 #define AG_COLS 128
-template <int RM>   // r <= RM
-__global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, const float2* __restrict__ yt,
+template <int RM, bool MIXED>   // r <= RM; MIXED: W~ stored as packed bf16 pairs
+__global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __restrict__ yt,
                                                const float2* __restrict__ xt, const cd* __restrict__ gyp,
                                                const cd* __restrict__ qy, const int* __restrict__ qy_zero,
                                                float2* __restrict__ rhs, int n1, int n2, int r, int nb,
-                                               double eta, double rho1, int mixed, int raw_a) {
+                                               double eta, double rho1, int raw_a) {
   __shared__ __align__(16) float2 ysh[RM * AG_COLS];   // [s][j] of the column chunk
   __shared__ __align__(16) float2 ash[AG_ROWS * RM];   // A rows, then the results
   __shared__ __align__(16) cd gs[RM * RM];             // G_Y^+
@@ -171,52 +171,50 @@ __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, cons
   v4f acc[NNT];
 #pragma unroll
   for (int u = 0; u < NNT; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+  // One pass per AG_COLS columns.  The Y~ chunk is loaded first (its LDS stage must not wait
+  // for the W~ loads, the memory counter being in order), then every W~ load of the pass,
+  // unconditional from one base (row clamped into range, immediate offsets; the W~ buffer
+  // has AG_COLS elements of slack past its end) and kept raw: masks and conversions are
+  // applied at the products, so that the products of group g wait only for its own loads.
   for (int j0 = 0; j0 < n2; j0 += AG_COLS) {
+    using raw_t = typename std::conditional<MIXED, uint32_t, float2>::type;
     const int nc = min(AG_COLS, n2 - j0), ngroups = (nc + 7) / 8;
-    // W~ operands of this pass: group g covers columns j0 + 8 g .. + 7; this lane takes 2
-    // All loads unconditional from one base (row clamped into range, immediate offsets; the
-    // W~ buffer has AG_COLS elements of slack past its end) and masked afterwards; the
-    // storage branch sits outside the unrolled loop, so that no load waits at a join.
-    float4 wa[AG_COLS / 8];
-    const size_t wbase = ((size_t)min(row, n1 - 1) * nb + b) * n2 + j0 + 2 * q;
-    auto load_wa = [&](auto mixed_tag) {
-      float2 lo[AG_COLS / 8], hi[AG_COLS / 8];
-#pragma unroll
-      for (int g = 0; g < AG_COLS / 8; ++g) {
-        if constexpr (decltype(mixed_tag)::value) {
-          const uint32_t* w = (const uint32_t*)wt + wbase;
-          lo[g] = unpack_bf16x2(w[8 * g]);
-          hi[g] = unpack_bf16x2(w[8 * g + 1]);
-        } else {
-          const float2* w = (const float2*)wt + wbase;
-          lo[g] = w[8 * g];
-          hi[g] = w[8 * g + 1];
-        }
-      }
-#pragma unroll
-      for (int g = 0; g < AG_COLS / 8; ++g) {
-        const int jj = 8 * g + 2 * q;
-        const int valid = (g < ngroups && row < n1) ? min(2, nc - jj) : 0;
-        const float2 z = make_float2(0.f, 0.f), a = valid > 0 ? lo[g] : z, c = valid > 1 ? hi[g] : z;
-        wa[g] = make_float4(a.x, a.y, c.x, c.y);
-      }
-    };
-    if (mixed) load_wa(std::true_type{});
-    else load_wa(std::false_type{});
-    // the Y~ column chunk, loaded while the W~ loads are in flight
     float2 yv[YPER];
 #pragma unroll
     for (int u = 0; u < YPER; ++u) {
       const int e = tid + 256 * u, s = e / AG_COLS, jj = e % AG_COLS;
-      yv[u] = ld_or(yt, ((size_t)b * r + s) * n2 + j0 + jj, s < r && jj < nc, make_float2(0.f, 0.f));
+      yv[u] = yt[((size_t)b * r + min(s, r - 1)) * n2 + j0 + min(jj, nc - 1)];
+    }
+    // group g covers columns j0 + 8 g .. + 7; this lane takes 2
+    raw_t lo[AG_COLS / 8], hi[AG_COLS / 8];
+    const raw_t* wrow = (const raw_t*)wt + ((size_t)min(row, n1 - 1) * nb + b) * n2 + j0 + 2 * q;
+#pragma unroll
+    for (int g = 0; g < AG_COLS / 8; ++g) {
+      lo[g] = wrow[8 * g];
+      hi[g] = wrow[8 * g + 1];
     }
     if (j0 > 0) __syncthreads();   // every wavefront is done with the previous chunk
 #pragma unroll
-    for (int u = 0; u < YPER; ++u) ysh[tid + 256 * u] = yv[u];
+    for (int u = 0; u < YPER; ++u) {
+      const int e = tid + 256 * u, s = e / AG_COLS, jj = e % AG_COLS;
+      ysh[e] = (s < r && jj < nc) ? yv[u] : make_float2(0.f, 0.f);
+    }
     __syncthreads();
 #pragma unroll
     for (int g = 0; g < AG_COLS / 8; ++g) {
       if (g < ngroups) {
+        const int valid = row < n1 ? min(2, nc - (8 * g + 2 * q)) : 0;
+        float2 a0, a1;
+        if constexpr (MIXED) {
+          a0 = unpack_bf16x2(lo[g]);
+          a1 = unpack_bf16x2(hi[g]);
+        } else {
+          a0 = lo[g];
+          a1 = hi[g];
+        }
+        const float2 z = make_float2(0.f, 0.f);
+        const float4 wa = make_float4(valid > 0 ? a0.x : z.x, valid > 0 ? a0.y : z.y, valid > 1 ? a1.x : z.x,
+                                      valid > 1 ? a1.y : z.y);
 #pragma unroll
         for (int u = 0; u < NNT; ++u) {
           const int s = min((16 * u + m) >> 1, r - 1);   // columns past 2r are dropped below
@@ -224,10 +222,10 @@ __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, cons
           // e = 0: (Yr, Yi, Yr', Yi');  e = 1: (-Yi, Yr, -Yi', Yr')
           const float b0 = eodd ? -y2.y : y2.x, b1 = eodd ? y2.x : y2.y;
           const float b2 = eodd ? -y2.w : y2.z, b3 = eodd ? y2.z : y2.w;
-          acc[u] = mfma4(wa[g].x, b0, acc[u]);
-          acc[u] = mfma4(wa[g].y, b1, acc[u]);
-          acc[u] = mfma4(wa[g].z, b2, acc[u]);
-          acc[u] = mfma4(wa[g].w, b3, acc[u]);
+          acc[u] = mfma4(wa.x, b0, acc[u]);
+          acc[u] = mfma4(wa.y, b1, acc[u]);
+          acc[u] = mfma4(wa.z, b2, acc[u]);
+          acc[u] = mfma4(wa.w, b3, acc[u]);
         }
       }
     }
@@ -317,12 +315,18 @@ __global__ void __launch_bounds__(256) k_agemm(const void* __restrict__ wt, cons
 
 void launch_agemm(const Plan& p, int raw_a) {
   dim3 grid((p.n1 + AG_ROWS - 1) / AG_ROWS, p.nb);
-#define TCTF_AGEMM(RM)                                                                                     \
-  k_agemm<RM><<<grid, 256, 0, p.stream>>>(p.wt, p.yt, p.xt, p.gyp, p.qy, p.qy_zero, p.rhs, p.n1, p.n2, p.r, \
-                                          p.nb, p.eta, p.rho1, p.mixed, raw_a)
-  if (p.r <= 8) TCTF_AGEMM(8);
-  else if (p.r <= 16) TCTF_AGEMM(16);
-  else TCTF_AGEMM(32);
+#define TCTF_AGEMM(RM, MX)                                                                                    \
+  k_agemm<RM, MX><<<grid, 256, 0, p.stream>>>(p.wt, p.yt, p.xt, p.gyp, p.qy, p.qy_zero, p.rhs, p.n1, p.n2, p.r, \
+                                              p.nb, p.eta, p.rho1, raw_a)
+  if (p.mixed) {
+    if (p.r <= 8) TCTF_AGEMM(8, true);
+    else if (p.r <= 16) TCTF_AGEMM(16, true);
+    else TCTF_AGEMM(32, true);
+  } else {
+    if (p.r <= 8) TCTF_AGEMM(8, false);
+    else if (p.r <= 16) TCTF_AGEMM(16, false);
+    else TCTF_AGEMM(32, false);
+  }
 #undef TCTF_AGEMM
 }
 
