@@ -49,7 +49,7 @@ struct StateHeader {
 };
 
 struct Layout {
-  size_t gp, wt, zt, xt, yt, rhs, bpart, gxm, dmat, gxpart, gym, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
+  size_t gp, wt, zt, xt, yt, rhs, bpart, gxm, dmat, gxp, qx, qx_zero, gym, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
       flag, scal, xt_prev, yt_prev, wt_prev, stat_work, kkt, total;
   size_t state_bytes;
 };
@@ -77,8 +77,6 @@ static Layout make_layout(const tctf_params& p) {
   int nchunk, chunk, ny, ycw;
   chunking(p.n1, (int)nb, &nchunk, &chunk);
   tctf::ystep_split(p.n2, p.r, (int)nb, &ny, &ycw);
-  const size_t ngx = tctf::gramx_groups(p.n1, p.r), gxg = tctf::ystep_gx_groups(p.r);
-  const size_t ngs = ngx > gxg ? ngx : gxg;
   const size_t welem = p.precision == TCTF_MIXED_BF16 ? 4 : 8;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
@@ -91,7 +89,9 @@ static Layout make_layout(const tctf_params& p) {
   L.bpart = take(nb * nchunk * r * n2 * 8);
   L.gxm = take(nb * r * r * 16);
   L.dmat = take(nb * r * r * 16);
-  L.gxpart = take((nb * ngs * 2 * r * r + 1024) * 16);
+  L.gxp = take(nb * r * r * 16);
+  L.qx = take(nb * r * r * 16);
+  L.qx_zero = take(nb * 4);
   L.gym = take(nb * ny * r * r * 16);
   L.gyp = take(nb * r * r * 16);
   L.qy = take(nb * r * r * 16);
@@ -189,8 +189,6 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.nb = p.n3 / 2 + 1;
   chunking(p.n1, q.nb, &q.nchunk, &q.chunk);
   tctf::ystep_split(p.n2, p.r, q.nb, &q.ny, &q.ycw);
-  q.ngx = tctf::gramx_groups(p.n1, p.r);
-  q.ngs = q.ngx > tctf::ystep_gx_groups(p.r) ? q.ngx : tctf::ystep_gx_groups(p.r);
   q.mu = p.mu;
   q.rho1 = p.rho1;
   q.rho2 = p.rho2;
@@ -207,7 +205,9 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.bpart = (float2*)(w + L.bpart);
   q.gxm = (cd*)(w + L.gxm);
   q.dmat = (cd*)(w + L.dmat);
-  q.gxpart = (cd*)(w + L.gxpart);
+  q.gxp = (cd*)(w + L.gxp);
+  q.qx = (cd*)(w + L.qx);
+  q.qx_zero = (int*)(w + L.qx_zero);
   q.gym = (cd*)(w + L.gym);
   q.gyp = (cd*)(w + L.gyp);
   q.qy = (cd*)(w + L.qy);
@@ -299,7 +299,6 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   tctf::zgemm_set_attr(p.r);
   tctf::launch_zero(p, p.flag, 64);
   tctf::launch_zero(p, p.qy_zero, (size_t)p.nb * 4);
-  tctf::launch_zero(p, p.gxpart, ((size_t)p.nb * p.ngs * 2 * p.r * p.r + 1024) * 16);
   tctf::launch_pack_g(p, G, omega);
   tctf::launch_tables(p);
   if (X0) tctf::launch_tube_dft_setup(p, X0, p.xt, p.n1, p.r, (long)p.r * p.n1, 1, p.n1);

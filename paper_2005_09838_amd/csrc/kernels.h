@@ -11,7 +11,6 @@ struct Plan {
   int n1, n2, n3, r, nb;       // nb = n3/2 + 1 stored frequencies
   int nchunk, chunk;           // row chunks of the X~^* W~ reduction
   int ny, ycw;                 // column blocks of the Y-step per frequency, columns per block
-  int ngx, ngs;                // row groups of the G_X Gram per frequency, their stride in gxpart
   double mu, rho1, rho2, eta;
   int mixed, force_eigen;
   hipStream_t stream;
@@ -25,8 +24,9 @@ struct Plan {
   float2* bpart;    // partial X~^* W~ [nb][nchunk][r][n2]
   cd* gxm;          // G_X = X~^* H_rho1 X~ [nb][r][r]
   cd* dmat;         // (H X~)^* (H X~) [nb][r][r]
-  cd* gxpart;       // [nb][ngs][2][r][r] row-group partials of X~^* X~ and (H X~)^*(H X~);
-                    // groups ngx .. ngs - 1 stay zero, and 1024 entries of slack follow
+  cd* gxp;          // G_X^+ [nb][r][r]
+  cd* qx;           // I - eta P_X [nb][r][r]
+  int* qx_zero;     // [nb] 1 when I - eta P_X is exactly 0
   cd* gym;          // partial Y~ Y~^* over column blocks [nb][ny][r][r]
   cd* gyp;          // (Y~ Y~^*)^+ [nb][r][r]
   cd* qy;           // I - eta P_Y [nb][r][r]
@@ -63,10 +63,9 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
 void launch_zgemm(const Plan& p, int with_pinv = 0);   // with_pinv: also G_Y^+ (pinvy_block)
 void launch_agemm(const Plan& p, int raw_a = 0);
 void launch_hsolve(const Plan& p);
-void launch_bgemm(const Plan& p);   // also the row-group partials of G_X (gramx_block)
+void launch_bgemm(const Plan& p);   // also G_X, G_X^+ and I - eta P_X (gramx_block)
 size_t bgemm_lds_bytes(int r, int chunk);
-int gramx_groups(int n1, int r);
-int ystep_gx_groups(int r);
+
 void bgemm_set_attr(size_t lds);
 void launch_ystep(const Plan& p, int init);
 void ystep_split(int n2, int r, int nb, int* ny, int* cw);

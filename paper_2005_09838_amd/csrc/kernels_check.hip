@@ -11,8 +11,8 @@ namespace tctf {
 
 __global__ void __launch_bounds__(256) k_stat_bin(const float2* __restrict__ xt, const float2* __restrict__ yt,
                                                   const void* __restrict__ wt, const float2* __restrict__ a,
-                                                  const float2* __restrict__ bpart, const cd* __restrict__ gxpart,
-                                                  int ngx, int ngs, double* __restrict__ out, int n1, int n2, int n3, int r,
+                                                  const float2* __restrict__ bpart, const cd* __restrict__ gxm,
+                                                  double* __restrict__ out, int n1, int n2, int n3, int r,
                                                   int nb, int nchunk, double rho1, int mixed) {
   __shared__ cd gy[TCTF_RMAX * TCTF_RMAX];
   __shared__ cd gx[TCTF_RMAX * TCTF_RMAX];
@@ -28,13 +28,7 @@ __global__ void __launch_bounds__(256) k_stat_bin(const float2* __restrict__ xt,
       cd_fma(acc, cd_make(u.x, u.y), cd_make(v.x, -v.y));
     }
     gy[e] = acc;
-    const cd* p0 = gxpart + (size_t)b * ngs * 2 * rr;   // G_X from the row-group partials
-    cd sv = p0[e], dv = p0[rr + e];
-    for (int g = 1; g < ngx; ++g) {
-      sv = cd_add(sv, p0[(size_t)g * 2 * rr + e]);
-      dv = cd_add(dv, p0[(size_t)g * 2 * rr + rr + e]);
-    }
-    gx[e] = cd_add(sv, cd_scale(dv, rho1));
+    gx[e] = gxm[(size_t)b * rr + e];
   }
   __syncthreads();
   double gyn = 0.0, gxn = 0.0, xn = 0.0, yn = 0.0, wn = 0.0;
@@ -125,8 +119,8 @@ __global__ void k_stat_final(const double* __restrict__ part, int nb, const doub
 
 void launch_stationarity(const Plan& p, int w_from_g) {
   launch_agemm(p, 1);   // A = W~ Y~^* into the right-hand-side buffer
-  launch_bgemm(p);      // X~^* W~ partial sums and the partials of G_X
-  k_stat_bin<<<p.nb, 256, 0, p.stream>>>(p.xt, p.yt, p.wt, p.rhs, p.bpart, p.gxpart, p.ngx, p.ngs, p.stat_work, p.n1,
+  launch_bgemm(p);      // X~^* W~ partial sums and G_X
+  k_stat_bin<<<p.nb, 256, 0, p.stream>>>(p.xt, p.yt, p.wt, p.rhs, p.bpart, p.gxm, p.stat_work, p.n1,
                                          p.n2, p.n3, p.r, p.nb, p.nchunk, p.rho1, p.mixed);
   launch_zgemm(p);
   launch_slice(p, SLICE_KKT, nullptr, nullptr, w_from_g);

@@ -330,72 +330,70 @@ void launch_agemm(const Plan& p, int raw_a) {
 #undef TCTF_AGEMM
 }
 
-// Output of gramx_block.
+// Outputs of gramx_block, per frequency b ([nb][r][r] FP64 complex unless noted).
 struct GramOut {
-  cd* gxpart;   // [nb][ngs][2][r][r] the row groups' partial X~^* X~ and (H X~)^*(H X~)
-  int ngx;      // row groups per frequency
-  int ngs;      // group stride of gxpart (>= ngx)
+  cd* gxm;       // G_X
+  cd* dmat;      // (H X~)^*(H X~)
+  cd* gxp;       // G_X^+
+  cd* qx;        // I - eta G_X^+ G_X (not written when it is exactly 0)
+  int* qx_zero;  // [nb] 1 when I - eta P_X = 0
+  double rho1, eta;
+  int force_eigen;
 };
 
-// Rows per group of gramx_block (plus the next row): 256, and 64 at r > 16 where the two
-// sweeps need the partials beside the staging area.
+// Rows per staged group of gramx_block (plus the next row): 256, and 64 at r > 16 where the
+// two sweeps need the partials beside the staging area.
 #define GX_ROWS(RM) ((RM) <= 16 ? 256 : 64)
 
-// LDS bytes of gramx_block at rank r <= RM: the staged rows and the complex Gram partials.
+// LDS bytes of gramx_block at rank r <= RM: the staged rows and the complex Gram partials,
+// later G_X with the pseudo-inverse scratch.
 static inline size_t gramx_lds_bytes(int r, int rm) {
   const int ks = rm == 8 ? 4 : 1;
   const size_t sb = (size_t)2 * rm * (GX_ROWS(rm) + 4) * sizeof(float);
   const size_t pb = (size_t)ks * 2 * r * r * sizeof(cd);
-  return rm <= 16 ? (sb > pb ? sb : pb) : sb + pb;
+  const size_t a = rm <= 16 ? (sb > pb ? sb : pb) : sb + pb;
+  return a > pinvy_lds_bytes(r) ? a : pinvy_lds_bytes(r);
 }
 
-// Row group g (rows g GR .. g GR + GR - 1) of frequency b, by a whole block: the group's
-// FP64 Grams C = X'^T X' and the same for the row differences X'(i + 1) - X'(i) (the
-// difference at row i belongs to the group of row i), as 16 x 16 x 4 FP64 matrix-core
-// tiles.  The rows (and the next one) are staged column by column (X'^T; columns past 2r and
-// rows past n1 zero).  Within 16 rows the K order is permuted: lane (m, q) feeds rows
-// 4 q .. 4 q + 3 of the 16, so one 16-byte LDS read (and one float of the following row)
-// serves four steps.  A full group needs no masks; the last group masks the difference at
-// the last row.  At r <= 8 the four wavefronts share the one tile and split the rows; at
-// r > 16 each wavefront takes its four tiles in two sweeps.  The lanes holding C[2s][2t]
+// Frequency b, by a whole block: the FP64 Grams C = X'^T X' and the same for the row
+// differences X'(i + 1) - X'(i) over all n1 rows, as 16 x 16 x 4 FP64 matrix-core tiles.
+// Rows arrive in groups of GR (plus the next row), staged column by column (X'^T; columns
+// past 2r and rows past n1 zero), the next group's loads in flight while the current one is
+// multiplied.  Within 16 rows the K order is permuted: lane (m, q) feeds rows 4 q .. 4 q + 3
+// of the 16, so one 16-byte LDS read (and one float of the following row) serves four
+// steps.  Full groups need no masks; the last group masks the difference at the last row.
+// At r <= 8 the four wavefronts share the one tile and split the rows; at r > 16 each
+// wavefront takes its four tiles in two sweeps over the rows.  The lanes holding C[2s][2t]
 // gather the 2 x 2 real block by shuffles and form X~^* X~ (s, t) = (C[2s][2t] +
-// C[2s+1][2t+1], C[2s][2t+1] - C[2s+1][2t]), likewise (H X~)^*(H X~); the group's two
-// complex partials go to gxpart (the Y-step sums them in group order).
+// C[2s+1][2t+1], C[2s][2t+1] - C[2s+1][2t]), likewise (H X~)^*(H X~); then
+// G_X = X~^* X~ + rho1 (H X~)^*(H X~), its pseudo-inverse (Lemma SVPMPI, pinv_herm) and
+// I - eta P_X.
 template <int RM>
-__device__ inline void gramx_block(int b, int g, const float2* __restrict__ xt, int n1, int r, const GramOut& go,
+__device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1, int r, const GramOut& go,
                                    unsigned char* sm) {
   constexpr int MT = RM / 8, NT = MT * MT;         // 16 x 16 tiles of the real Gram
   constexpr int KS = NT >= 4 ? 1 : 4 / NT;         // wavefronts sharing a tile (row split)
   constexpr int TPW = NT >= 4 ? NT / 4 : 1;        // tiles per wavefront
-  constexpr int TPS = TPW < 2 ? TPW : 2;           // tiles per sweep
+  constexpr int TPS = TPW < 2 ? TPW : 2;           // tiles per sweep over the rows
   constexpr int NSW = TPW / TPS;                   // sweeps
   constexpr int GR = GX_ROWS(RM);                  // rows per group
   constexpr int LD = GR + 4;                       // LDS stride of a staged column (floats)
   constexpr int PER = ((GR + 1) * RM + 255) / 256; // staged elements per thread (GR + 1 rows)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
   const int rr = r * r, kp = KS > 1 ? w : 0;
-  const int i0 = g * GR, nrows = min(GR, n1 - i0);
-  const bool full = i0 + GR < n1;   // GR rows and the next one: no masks
   float* xs = (float*)sm;   // [2 RM][LD]: X'^T, column 2 s + d of X' is row 2 s + d here
   // [KS][2][rr]: after the staging area, or in it when one sweep leaves it free
   cd* part = (cd*)(sm + (NSW > 1 ? (size_t)2 * RM * LD * sizeof(float) : 0));
-  {  // element e: column s = e / (GR + 1), row h = e % (GR + 1); past the matrix: zeros
-    float2 pf[PER];
+  // element e of a group: column s = e / (GR + 1), row h = e % (GR + 1); past the matrix: zeros
+  float2 pf[PER];
+  auto load_group = [&](int i0) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + 256 * u, s = e / (GR + 1), h = e % (GR + 1);
       pf[u] = ld_or(xt, ((size_t)b * r + s) * n1 + i0 + h, s < r && i0 + h < n1, make_float2(0.f, 0.f));
     }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + 256 * u, s = e / (GR + 1), h = e % (GR + 1);
-      if (s < RM) {
-        xs[(2 * s) * LD + h] = pf[u].x;
-        xs[(2 * s + 1) * LD + h] = pf[u].y;
-      }
-    }
-  }
-  __syncthreads();
+  };
+  load_group(0);
 #pragma unroll
   for (int sw = 0; sw < NSW; ++sw) {
     v4d acs[TPS], acd[TPS];
@@ -404,31 +402,47 @@ __device__ inline void gramx_block(int b, int g, const float2* __restrict__ xt, 
       acs[u] = v4d{0.0, 0.0, 0.0, 0.0};
       acd[u] = v4d{0.0, 0.0, 0.0, 0.0};
     }
+    for (int i0 = 0; i0 < n1; i0 += GR) {
+      const int nrows = min(GR, n1 - i0);
+      __syncthreads();   // the previous rows are consumed
 #pragma unroll
-    for (int u = 0; u < TPS; ++u) {
-      const int tile = KS > 1 ? 0 : w + 4 * (sw * TPS + u);
-      const float* pa = xs + (16 * (tile / MT) + m) * LD;   // column 2 s + d of X'
-      const float* pb = xs + (16 * (tile % MT) + m) * LD;
-      auto step16 = [&](int jb, auto masked) {
-        const int h0 = 16 * jb + 4 * q;
-        const float4 a4 = *(const float4*)(pa + h0), b4 = *(const float4*)(pb + h0);
-        const double av[5] = {a4.x, a4.y, a4.z, a4.w, pa[h0 + 4]};
-        const double bv[5] = {b4.x, b4.y, b4.z, b4.w, pb[h0 + 4]};
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          double a1 = av[jj + 1] - av[jj], b1 = bv[jj + 1] - bv[jj];
-          if constexpr (decltype(masked)::value) {   // no difference at the last row
-            if (i0 + h0 + jj + 1 >= n1) a1 = b1 = 0.0;
-          }
-          acs[u] = mfma4d(av[jj], bv[jj], acs[u]);
-          acd[u] = mfma4d(a1, b1, acd[u]);
+      for (int u = 0; u < PER; ++u) {
+        const int e = tid + 256 * u, s = e / (GR + 1), h = e % (GR + 1);
+        if (s < RM) {
+          xs[(2 * s) * LD + h] = pf[u].x;
+          xs[(2 * s + 1) * LD + h] = pf[u].y;
         }
-      };
-      if (full) {
+      }
+      __syncthreads();
+      if (i0 + GR < n1) load_group(i0 + GR);
+      else if (sw + 1 < NSW) load_group(0);
+      const bool full = i0 + GR < n1;   // GR rows and the next one: no masks
+#pragma unroll
+      for (int u = 0; u < TPS; ++u) {
+        const int tile = KS > 1 ? 0 : w + 4 * (sw * TPS + u);
+        const float* pa = xs + (16 * (tile / MT) + m) * LD;   // column 2 s + d of X'
+        const float* pb = xs + (16 * (tile % MT) + m) * LD;
+        auto step16 = [&](int jb, auto masked) {
+          const int h0 = 16 * jb + 4 * q;
+          const float4 a4 = *(const float4*)(pa + h0), b4 = *(const float4*)(pb + h0);
+          const double av[5] = {a4.x, a4.y, a4.z, a4.w, pa[h0 + 4]};
+          const double bv[5] = {b4.x, b4.y, b4.z, b4.w, pb[h0 + 4]};
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            double a1 = av[jj + 1] - av[jj], b1 = bv[jj + 1] - bv[jj];
+            if constexpr (decltype(masked)::value) {   // no difference at the last row
+              if (i0 + h0 + jj + 1 >= n1) a1 = b1 = 0.0;
+            }
+            acs[u] = mfma4d(av[jj], bv[jj], acs[u]);
+            acd[u] = mfma4d(a1, b1, acd[u]);
+          }
+        };
+        if (full) {
 #pragma unroll 2
-        for (int jb = kp; jb < GR / 16; jb += KS) step16(jb, std::false_type{});
-      } else {
-        for (int jb = kp; 16 * jb < nrows; jb += KS) step16(jb, std::true_type{});
+          for (int jb = kp; jb < GR / 16; jb += KS) step16(jb, std::false_type{});
+        } else {
+          for (int jb = kp; 16 * jb < nrows; jb += KS) step16(jb, std::true_type{});
+        }
       }
     }
     if (NSW == 1) __syncthreads();   // the partials take the staging area
@@ -453,18 +467,52 @@ __device__ inline void gramx_block(int b, int g, const float2* __restrict__ xt, 
     }
   }
   __syncthreads();
-  // this group's partials (the row parts summed in a fixed order)
-  cd* gpart = go.gxpart + ((size_t)b * go.ngs + g) * 2 * rr;
-  for (int e = tid; e < rr; e += 256) {
-    cd sv = part[e], dv = part[rr + e];
+  constexpr int GPT = (RM * RM + 255) / 256;   // G_X entries per thread
+  cd gv[GPT];
 #pragma unroll
-    for (int j = 1; j < KS; ++j) {
-      sv = cd_add(sv, part[2 * j * rr + e]);
-      dv = cd_add(dv, part[(2 * j + 1) * rr + e]);
+  for (int k = 0; k < GPT; ++k) {
+    const int e = tid + 256 * k;
+    gv[k] = cd_make(0.0, 0.0);
+    if (e < rr) {
+      cd sv = part[e], dv = part[rr + e];
+#pragma unroll
+      for (int j = 1; j < KS; ++j) {   // the row parts, in a fixed order
+        sv = cd_add(sv, part[2 * j * rr + e]);
+        dv = cd_add(dv, part[(2 * j + 1) * rr + e]);
+      }
+      gv[k] = cd_add(sv, cd_scale(dv, go.rho1));
+      go.gxm[(size_t)b * rr + e] = gv[k];
+      go.dmat[(size_t)b * rr + e] = dv;
     }
-    gpart[e] = sv;
-    gpart[rr + e] = dv;
   }
+  __syncthreads();   // the partials are read; G_X and the pinv scratch take their place
+  cd* gx = (cd*)sm;
+  cd* gp = gx + rr;
+  PinvScratch ps;
+  ps.work = gp + rr;
+  ps.vec = ps.work + rr;
+  ps.colk = ps.vec + rr;
+  ps.rowk = ps.colk + r;
+  ps.rot = (double*)(ps.rowk + r);
+  ps.red = ps.rot + 96;
+#pragma unroll
+  for (int k = 0; k < GPT; ++k) {
+    const int e = tid + 256 * k;
+    if (e < rr) gx[e] = gv[k];
+  }
+  __syncthreads();
+  const int fullr = pinv_herm(gx, gp, r, go.force_eigen, ps);
+  const bool qzero = fullr && go.eta == 1.0;
+  for (int e = tid; e < rr; e += 256) {
+    go.gxp[(size_t)b * rr + e] = gp[e];
+    if (!qzero) {   // q = I - eta G_X^+ G_X
+      const int s = e / r, t = e % r;
+      cd acc = cd_make(0.0, 0.0);
+      for (int u = 0; u < r; ++u) cd_fma(acc, gp[s * r + u], gx[u * r + t]);
+      go.qx[(size_t)b * rr + e] = cd_make((s == t ? 1.0 : 0.0) - go.eta * acc.re, -go.eta * acc.im);
+    }
+  }
+  if (tid == 0) go.qx_zero[b] = qzero ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- X~^* W~, and G_X with its inverse
@@ -475,9 +523,10 @@ __device__ inline void gramx_block(int b, int g, const float2* __restrict__ xt, 
 // of BG_COLS columns, its whole W~ slab are staged in LDS with every load of a thread
 // issued at once; each wavefront owns a quarter of the 16-column tiles of a pass.  After
 // every 16 rows the FP32 tile sums are added into FP64 accumulators.
-// At r <= 16 the first nb ngx blocks of the launch instead form the row-group partials of
-// X~^* X~ and (H X~)^*(H X~) in FP64 on the matrix cores (gramx_block), beside the products;
-// at r > 16 k_gramx does this work in a launch of its own.
+// At r <= 16 the first nb blocks of the launch instead form, for frequency blockIdx.x, the
+// whole Gram G_X = X~^* X~ + rho1 (H X~)^*(H X~) in FP64 on the matrix cores, its
+// pseudo-inverse and I - eta P_X (gramx_block), beside the products; at r > 16 k_gramx
+// does this work in a launch of its own.
 #define BG_COLS 64                  // complex columns per pass
 #define BG_MAXROWS 64               // rows per chunk at most
 #define BG_WLD (2 * BG_COLS + 16)   // LDS row stride of the staged W~ slab (floats)
@@ -487,10 +536,10 @@ k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, float2* __re
         int n2, int r, int nb, int nchunk, int chunk, int mixed) {
   extern __shared__ __align__(16) float smb[];
   constexpr bool GRAM = RM <= 16;   // at r > 16 the registers of both paths would not fit twice
-  const int ng = GRAM ? nb * go.ngx : 0;   // G_X row-group blocks at the front of the grid
+  const int ng = GRAM ? nb : 0;   // G_X blocks at the front of the grid
   if constexpr (GRAM) {
     if ((int)blockIdx.x < ng) {
-      gramx_block<RM>(blockIdx.x / go.ngx, blockIdx.x % go.ngx, xt, n1, r, go, (unsigned char*)smb);
+      gramx_block<RM>(blockIdx.x, xt, n1, r, go, (unsigned char*)smb);
       return;
     }
   }
@@ -614,15 +663,14 @@ k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, float2* __re
   }
 }
 
-// The row-group partials of G_X alone (r > 16: beside the products they would cost them
+// G_X alone, one block per frequency (r > 16: beside the products it would cost them
 // registers).
 template <int RM>
 __global__ void __launch_bounds__(256) k_gramx(const float2* __restrict__ xt, GramOut go, int n1, int r) {
   extern __shared__ __align__(16) unsigned char smg[];
-  gramx_block<RM>(blockIdx.x / go.ngx, blockIdx.x % go.ngx, xt, n1, r, go, smg);
+  gramx_block<RM>(blockIdx.x, xt, n1, r, go, smg);
 }
 
-int gramx_groups(int n1, int r) { return (n1 + GX_ROWS(r <= 8 ? 8 : (r <= 16 ? 16 : 32)) - 1) / GX_ROWS(r <= 8 ? 8 : (r <= 16 ? 16 : 32)); }
 
 size_t bgemm_lds_bytes(int r, int chunk) {
   const int rm = r <= 8 ? 8 : (r <= 16 ? 16 : 32);
@@ -643,12 +691,17 @@ void bgemm_set_attr(size_t lds) {
 
 void launch_bgemm(const Plan& p) {
   const bool fused = p.r <= 16;
-  const int grid = (fused ? p.nb * p.ngx : 0) + p.nchunk * p.nb;   // G_X groups first, then (chunk, frequency)
+  const int grid = (fused ? p.nb : 0) + p.nchunk * p.nb;   // G_X blocks first, then (chunk, frequency)
   const size_t lds = bgemm_lds_bytes(p.r, p.chunk);
   GramOut go;
-  go.gxpart = p.gxpart;
-  go.ngx = p.ngx;
-  go.ngs = p.ngs;
+  go.gxm = p.gxm;
+  go.dmat = p.dmat;
+  go.gxp = p.gxp;
+  go.qx = p.qx;
+  go.qx_zero = p.qx_zero;
+  go.rho1 = p.rho1;
+  go.eta = p.eta;
+  go.force_eigen = p.force_eigen;
 #define TCTF_BGEMM(RM)                                                                                  \
   k_bgemm<RM><<<grid, 256, lds, p.stream>>>(p.wt, p.xt, p.bpart, go, p.n1, p.n2, p.r, p.nb, p.nchunk, \
                                             p.chunk, p.mixed)
@@ -657,7 +710,7 @@ void launch_bgemm(const Plan& p) {
   } else if (p.r <= 16) {
     TCTF_BGEMM(16);
   } else {
-    k_gramx<32><<<p.nb * p.ngx, 256, lds, p.stream>>>(p.xt, go, p.n1, p.r);
+    k_gramx<32><<<p.nb, 256, lds, p.stream>>>(p.xt, go, p.n1, p.r);
     TCTF_BGEMM(32);
   }
 #undef TCTF_BGEMM

@@ -169,17 +169,17 @@ void launch_hsolve(const Plan& p) {
   k_hsolve<<<p.nb * p.r * 2, 64, lds, p.stream>>>(p.rhs, p.htab, p.xt, p.n1, p.r, p.n3);
 }
 
-// Dynamic LDS layout of k_ystep: the pseudo-inverse area (G_X, G_X^+ and the pinv_herm
-// scratch, as pinvy_lds_bytes), q = I - eta P_X, then the column block of cw columns with an
-// odd row stride cw | 1, so that the rows of one column fall in different LDS banks.
+// Dynamic LDS layout of k_ystep: G_X^+ and q = I - eta P_X (r x r FP64 complex), then the
+// column block of cw columns with an odd row stride cw | 1, so that the rows of one column
+// fall in different LDS banks.
 struct YLayout {
-  size_t gx, q, bsum, yold, ynew, total;
+  size_t gp, q, bsum, yold, ynew, total;
 };
 __host__ __device__ inline YLayout ystep_layout(int r, int cw) {
   YLayout L;
   const size_t m = (size_t)r * r * sizeof(cd), ld = (size_t)(cw | 1);
   size_t o = 0;
-  L.gx = o; o += pinvy_lds_bytes(r);
+  L.gp = o; o += m;
   L.q = o; o += m;
   L.bsum = o; o += (size_t)r * ld * sizeof(cd);       // columns of X~^* W~ (FP64)
   L.yold = o; o += (size_t)r * ld * sizeof(float2);   // the same columns of the old Y~
@@ -188,12 +188,8 @@ __host__ __device__ inline YLayout ystep_layout(int r, int cw) {
   return L;
 }
 
-#define YS_GXG(RM) ((RM) <= 16 ? 4 : 1)   // row groups of the G_X partials the Y-step loads up front
-
 // Column blocks of the Y-step: enough blocks to cover the compute units, at least 8 columns
 // each, at most 512 / r (two elements per thread).
-int ystep_gx_groups(int r) { return YS_GXG(r <= 16 ? 16 : 32); }
-
 void ystep_split(int n2, int r, int nb, int* ny, int* cw) {
   const int want = (256 + nb - 1) / nb;
   int c = (n2 + want - 1) / want;
@@ -204,61 +200,42 @@ void ystep_split(int n2, int r, int nb, int* ny, int* cw) {
   *ny = (n2 + c - 1) / c;
 }
 
-// Block (column block jb, frequency b), 256 threads, r <= RM.  The loads are issued in the
-// order they are needed, all before the first use: the row-group partials of X~^* X~ and
-// (H X~)^*(H X~), then the old columns and the first YS_CP1 chunk partials of X~^* W~ for
-// the block's columns.  While the latter are in flight the block sums the former (group
-// order) into G_X = X~^* H_rho1 X~ and forms G_X^+ (Lemma SVPMPI, pinv_herm) and
-// I - eta P_X; block 0 of the frequency also stores G_X and (H X~)^*(H X~).  Then the chunk
-// partials are summed (fixed order) and Y~ <- (I - eta P_X) Y~ + eta G_X^+ X~^* W~
-// (eq. (updataXYW1)) is formed on the block's columns in FP64 and stored in FP32, and the
-// block's FP64 partial of G_Y = Y~ Y~^* is formed from the stored values.  init: only
-// (H X~)^*(H X~) and the partial of G_Y.
+// Block (column block jb, frequency b), 256 threads, r <= RM; G_X^+ and I - eta P_X come
+// from the X~^* W~ launch (gramx_block).  Every load of the block is issued before any use:
+// G_X^+ and q, the old columns and the chunk partials of X~^* W~ for the block's columns
+// (YS_CP1 in the first batch, summed in a fixed order).  Then Y~ <- (I - eta P_X) Y~ +
+// eta G_X^+ X~^* W~ (eq. (updataXYW1)) is formed on the block's columns in FP64 and stored
+// in FP32, and the block's FP64 partial of G_Y = Y~ Y~^* from the stored values.  init: only
+// the partial of G_Y.
 #define YS_CP1 12   // chunk partials of X~^* W~ in the first batch of loads
 #define YS_CP 8     // and in each later batch
 template <int RM>
 __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const float2* __restrict__ bpart,
-                                               const cd* __restrict__ gxpart, int ngx, int ngs, cd* __restrict__ gxm,
-                                               cd* __restrict__ dmat, cd* __restrict__ gyq, int n2, int r, int n3,
-                                               int nchunk, int cw, int ny, double eta, double rho1,
-                                               int force_eigen, int init) {
-  constexpr int GPT = (RM * RM + 255) / 256;   // G_X entries per thread
-  constexpr int GXG = YS_GXG(RM);              // row groups loaded up front
+                                               const cd* __restrict__ gxp, const cd* __restrict__ qx,
+                                               const int* __restrict__ qx_zero, cd* __restrict__ gyq, int n2,
+                                               int r, int n3, int nchunk, int cw, int ny, double eta, int init) {
+  constexpr int GPT = (RM * RM + 255) / 256;   // r x r entries per thread
   extern __shared__ __align__(16) unsigned char sm[];
   const YLayout L = ystep_layout(r, cw);
   const int jb = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, rr = r * r;
-  cd* gx = (cd*)(sm + L.gx);
-  cd* gp = gx + rr;
-  PinvScratch ps;
-  ps.work = gp + rr;
-  ps.vec = ps.work + rr;
-  ps.colk = ps.vec + rr;
-  ps.rowk = ps.colk + r;
-  ps.rot = (double*)(ps.rowk + r);
-  ps.red = ps.rot + 96;
+  cd* gp = (cd*)(sm + L.gp);
   cd* q = (cd*)(sm + L.q);
   cd* bsum = (cd*)(sm + L.bsum);
   float2* yold = (float2*)(sm + L.yold);
   float2* ynew = (float2*)(sm + L.ynew);
   const int j0 = jb * cw, nj = min(cw, n2 - j0), nel = r * nj, ld = cw | 1;
   const bool real_bin = bin_is_real(b, n3);
+  const bool qzero = init || qx_zero[b] != 0;
   const float2 z2 = make_float2(0.f, 0.f);
   const cd zc = cd_make(0.0, 0.0);
-  const cd* p0 = gxpart + (size_t)b * ngs * 2 * rr;
 
-  // 1. the first GXG row groups of the G_X partials, loaded without masks: the buffer holds
-  // at least GXG zero-filled groups per frequency and slack past its end (values past rr
-  // are dropped below)
-  cd sp[GPT][GXG], dp[GPT][GXG];
+  cd g4[GPT], q4[GPT];
 #pragma unroll
-  for (int k = 0; k < GPT; ++k)
-#pragma unroll
-    for (int g = 0; g < GXG; ++g) {
-      const int e = tid + 256 * k;
-      sp[k][g] = p0[(size_t)g * 2 * rr + e];
-      dp[k][g] = p0[(size_t)g * 2 * rr + rr + e];
-    }
-  // 2. the old columns and the first chunk partials of X~^* W~ (two elements per thread)
+  for (int k = 0; k < GPT; ++k) {
+    const int e = tid + 256 * k;
+    g4[k] = ld_or(gxp, (size_t)b * rr + e, !init && e < rr, zc);
+    q4[k] = ld_or(qx, (size_t)b * rr + e, !qzero && e < rr, zc);
+  }
   float2 y[2], v[2][YS_CP1];
   size_t base[2];
 #pragma unroll
@@ -270,47 +247,6 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const fl
     for (int k = 0; k < YS_CP1; ++k)
       v[u][k] = ld_or(bpart, base[u] + (size_t)k * r * n2, !init && e < nel && k < nchunk, z2);
   }
-  // 3. G_X (group order; groups past GXG, if any, read now).  The sums are formed by every
-  // thread and only the stores are conditional, so that the loads above are not moved into
-  // a branch past the ones that follow them.
-#pragma unroll
-  for (int k = 0; k < GPT; ++k) {
-    const int e = tid + 256 * k;
-    cd sv = sp[k][0], dv = dp[k][0];
-#pragma unroll
-    for (int g = 1; g < GXG; ++g) {
-      sv = cd_add(sv, sp[k][g]);
-      dv = cd_add(dv, dp[k][g]);
-    }
-    for (int g = GXG; g < ngx; ++g) {
-      sv = cd_add(sv, ld_or(p0, (size_t)g * 2 * rr + e, e < rr, zc));
-      dv = cd_add(dv, ld_or(p0, (size_t)g * 2 * rr + rr + e, e < rr, zc));
-    }
-    const cd gv = cd_add(sv, cd_scale(dv, rho1));
-    if (e < rr) {
-      gx[e] = gv;
-      if (jb == 0) {
-        gxm[(size_t)b * rr + e] = gv;
-        dmat[(size_t)b * rr + e] = dv;
-      }
-    }
-  }
-  __syncthreads();
-  // 4. G_X^+ and q while the column loads are in flight
-  bool qzero = true;
-  if (!init) {
-    const int full = pinv_herm(gx, gp, r, force_eigen, ps);
-    qzero = full && eta == 1.0;
-    if (!qzero) {   // q = I - eta G_X^+ G_X
-      for (int e = tid; e < rr; e += 256) {
-        const int s = e / r, t = e % r;
-        cd a = zc;
-        for (int u = 0; u < r; ++u) cd_fma(a, gp[s * r + u], gx[u * r + t]);
-        q[e] = cd_make((s == t ? 1.0 : 0.0) - eta * a.re, -eta * a.im);
-      }
-    }
-  }
-  // 5. the chunk sums (fixed order), later chunks in batches
   cd acc[2];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -339,6 +275,14 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const fl
     }
   }
 #pragma unroll
+  for (int k = 0; k < GPT; ++k) {
+    const int e = tid + 256 * k;
+    if (e < rr) {
+      gp[e] = g4[k];
+      q[e] = q4[k];
+    }
+  }
+#pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int e = tid + 256 * u;
     if (e < nel) {
@@ -348,7 +292,6 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const fl
     }
   }
   __syncthreads();
-  // 6. the new columns, then the partial of G_Y from the stored values
   if (!init) {
     for (int e = tid; e < nel; e += 256) {
       const int s = e / nj, jj = e % nj;
@@ -369,6 +312,7 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const fl
     }
     __syncthreads();
   }
+  // partial G_Y(s, t) = sum over the block's columns of Y~(s, j) conj(Y~(t, j)), stored values
   const float2* yb = init ? yold : ynew;
   for (int e = tid; e < rr; e += 256) {
     const int s = e / r, t = e % r;
@@ -412,9 +356,9 @@ void ystep_set_attr(size_t lds) {
 void launch_ystep(const Plan& p, int init) {
   const size_t lds = ystep_layout(p.r, p.ycw).total;
   const dim3 grid(p.ny, p.nb);
-#define TCTF_YSTEP(RM)                                                                                        \
-  k_ystep<RM><<<grid, 256, lds, p.stream>>>(p.yt, p.bpart, p.gxpart, p.ngx, p.ngs, p.gxm, p.dmat, p.gym, p.n2, \
-                                            p.r, p.n3, p.nchunk, p.ycw, p.ny, p.eta, p.rho1, p.force_eigen, init)
+#define TCTF_YSTEP(RM)                                                                                       \
+  k_ystep<RM><<<grid, 256, lds, p.stream>>>(p.yt, p.bpart, p.gxp, p.qx, p.qx_zero, p.gym, p.n2, p.r, p.n3,    \
+                                            p.nchunk, p.ycw, p.ny, p.eta, init)
   if (p.r <= 8) TCTF_YSTEP(8);
   else if (p.r <= 16) TCTF_YSTEP(16);
   else TCTF_YSTEP(32);
