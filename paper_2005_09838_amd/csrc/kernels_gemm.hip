@@ -185,13 +185,15 @@ __global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __r
       const int e = tid + 256 * u, s = e / AG_COLS, jj = e % AG_COLS;
       yv[u] = yt[((size_t)b * r + min(s, r - 1)) * n2 + j0 + min(jj, nc - 1)];
     }
-    // group g covers columns j0 + 8 g .. + 7; this lane takes 2
+    // group g covers columns j0 + 8 g .. + 7; this lane takes 2 (groups past the last valid
+    // one load the last one again: no extra memory traffic, the values are dropped)
     raw_t lo[AG_COLS / 8], hi[AG_COLS / 8];
     const raw_t* wrow = (const raw_t*)wt + ((size_t)min(row, n1 - 1) * nb + b) * n2 + j0 + 2 * q;
 #pragma unroll
     for (int g = 0; g < AG_COLS / 8; ++g) {
-      lo[g] = wrow[8 * g];
-      hi[g] = wrow[8 * g + 1];
+      const int gc = min(g, ngroups - 1);
+      lo[g] = wrow[8 * gc];
+      hi[g] = wrow[8 * gc + 1];
     }
     if (j0 > 0) __syncthreads();   // every wavefront is done with the previous chunk
 #pragma unroll
