@@ -159,8 +159,11 @@ tctf_status tctf_complete(const tctf_params* p, const float* G, const uint8_t* o
  * stream between two HIP events and return the mean duration in microseconds.  Stages:
  *   0 slice kernel (inverse tube transform, W-step, forward transform; the W~ stream)
  *   1 Z~ = X~Y~ products        2 A = W~Y~^* products and the X right-hand side
- *   3 tridiagonal H_rho1 solve  4 X~^* W~ and Gram partials     5 Y-step and G_Y
- *   6 pseudo-inverse of G_Y     7 one whole iteration
+ *   3 tridiagonal H_rho1 solve
+ *   4 X~^* W~ partials, with G_X, its pseudo-inverse and I - eta P_X
+ *   5 Y-step and the column-block partials of G_Y
+ *   6 G_Y from its partials, its pseudo-inverse and I - eta P_Y
+ *   7 one whole iteration
  * Stages 0-6 recompute from the current state without advancing it (7 does advance). */
 tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* mean_us);
 

@@ -2,8 +2,8 @@
 //   Z~_b = X~_b Y~_b                       (step 3)                   k_zgemm
 //   A_b  = W~_b Y~_b^*  and the X right-hand side                      k_agemm
 //          R_b = eta A_b G_Y^+ + H_rho1 X~_b (I - eta P_Y)   (step 1, eq. (updataXYW1))
-//   X~_b^* W~_b, X~_b^* X~_b, (H X~_b)^*(H X~_b) partial sums over row chunks (step 2)
-//                                                                      k_bgemm
+//   X~_b^* W~_b partial sums over row chunks (step 2), and in extra blocks of the same
+//   launch G_X = X~_b^* X~_b + rho1 (H X~_b)^*(H X~_b), G_X^+ and I - eta P_X  k_bgemm
 // The complex products run on the matrix cores as real FP32 products (16 x 16 x 4 tiles):
 // a complex m x k by k x n product is an m x 2k by 2k x n' real one whose operands are the
 // interleaved (re, im) storage itself, with the signs of the complex product placed in the
@@ -74,11 +74,12 @@ __global__ void __launch_bounds__(256) k_zgemm(const float2* __restrict__ xt, co
     const float2 x = xt[((size_t)b * r + min(s, r - 1)) * n1 + min(row, n1 - 1)];
     a[ks] = (s < r && row < n1) ? ((kk & 1) ? x.y : x.x) : 0.f;
   }
-  // this lane's operand pick of Y': component and sign are fixed by (kk & 1, column & 1)
-  const int d = q & 1, cpar = m & 1;
-  const bool take_im = d != cpar;
-  const float sgn = (d == 1 && cpar == 0) ? -1.f : 1.f;
+  // Tile u of a group of four covers the group's 64 output floats 4 m + u (lane m's B
+  // column), so a lane ends with four consecutive floats of a row: one 16-byte store.  The
+  // operand pick of Y' is fixed by (kk & 1, column & 1) = (q & 1, u & 1).
+  const int d = q & 1;
   float* zf = (float*)zt;
+  const bool vec4 = (n2 & 1) == 0;   // rows start 16-byte aligned
   for (int j0 = 0; j0 < n2; j0 += ZG_COLS) {
     const int nc = min(ZG_COLS, n2 - j0);
     if (j0 > 0) {
@@ -98,20 +99,30 @@ __global__ void __launch_bounds__(256) k_zgemm(const float2* __restrict__ xt, co
         const int s = min((4 * ks + q) >> 1, r - 1);   // rows past 2r meet a zero A operand
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int jj = min((16 * (nt0 + u) + m) >> 1, ZG_COLS - 1);
+          const int cpar = u & 1;
+          const int jj = min(8 * nt0 + 2 * m + (u >> 1), ZG_COLS - 1);
           const float2 y = ysh[s * ZG_COLS + jj];
-          const float bv = sgn * (take_im ? y.y : y.x);
+          const float bv = (d == 1 && cpar == 0) ? -y.y : (d != cpar ? y.y : y.x);
           acc[u] = mfma4(a[ks], bv, acc[u]);
         }
       }
+      const int col = 16 * nt0 + 4 * m;   // first of this lane's four floats in the chunk's 2 nc
+      if (col < 2 * nc) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int col = 16 * (nt0 + u) + m;   // index into the chunk's 2 nc floats
-        if (col < 2 * nc) {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int i = i0 + 16 * w + 4 * q + t;
-            if (i < n1) zf[(((size_t)i * nb + b) * n2 + j0) * 2 + col] = acc[u][t];
+        for (int t = 0; t < 4; ++t) {
+          const int i = i0 + 16 * w + 4 * q + t;
+          if (i < n1) {
+            float* dst = zf + (((size_t)i * nb + b) * n2 + j0) * 2 + col;
+            if (col + 4 <= 2 * nc) {
+              if (vec4) {
+                *(float4*)dst = make_float4(acc[0][t], acc[1][t], acc[2][t], acc[3][t]);
+              } else {
+                ((float2*)dst)[0] = make_float2(acc[0][t], acc[1][t]);
+                ((float2*)dst)[1] = make_float2(acc[2][t], acc[3][t]);
+              }
+            } else {   // 2 nc is even: the last two floats of the row
+              *(float2*)dst = make_float2(acc[0][t], acc[1][t]);
+            }
           }
         }
       }

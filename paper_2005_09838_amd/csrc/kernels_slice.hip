@@ -21,6 +21,7 @@
 //   forward  y_j = (z_j + rho2 y_{j-1}) / alpha_j      (y = g on observed entries)
 //   backward w_j = y_j + rho2 / alpha_j * w_{j+1}       (w = g on observed entries)
 #include "kernels.h"
+#include "pinv.h"
 #include "tube_dft_gen.h"
 #include "tube_lds.h"
 
@@ -41,6 +42,8 @@ struct SliceArgs {
   float rho2;
   double mu, rho2d;
   int mode, mixed, w_from_g;
+  int npinv;     // SLICE_ITER: blocks n1 .. n1 + npinv - 1 form G_Y^+ of frequency blockIdx.x - n1
+  PinvyArgs pa;
 };
 
 template <int N>
@@ -407,7 +410,15 @@ __global__ void __launch_bounds__(1024) k_slice_coop(SliceArgs a) {
   using TL = TubeLds<N>;
   constexpr int T = TL::M1, M1 = TL::M1, M2 = TL::M2, M = N / 2;
   constexpr int LD = slice_ld<N>();
-  extern __shared__ float smem[];
+  extern __shared__ __align__(16) float smem[];
+  if constexpr (MODE == SLICE_ITER) {
+    // blocks past the last row: G_Y^+ and I - eta P_Y for the next X-step (pinvy_block),
+    // dispatched after every row block, into the last, partly idle round of row blocks
+    if ((int)blockIdx.x >= a.n1) {
+      pinvy_block((int)blockIdx.x - a.n1, a.pa, (unsigned char*)smem);
+      return;
+    }
+  }
   const int n2 = a.n2, nwr = (n2 + 31) >> 5, n2p = (n2 + 63) & ~63;
   float* zs = smem;                                   // [n2][LD]
   float* tab = zs + (size_t)n2 * LD;                  // [4][n2]
@@ -631,8 +642,20 @@ void slice_set_attr(int n3, size_t lds) {
   }
 }
 
+bool slice_can_host_pinvy(int n1, int n2, int n3, int nb, int ncu) {
+  const int rem = ncu > 0 ? n1 % ncu : 0;
+  return coop_threads(n2, n3) > 0 && rem > 0 && rem + nb <= ncu;
+}
+
+size_t slice_launch_lds_bytes(int n2, int n3, int r, int host_pinvy) {
+  const size_t a = slice_lds_bytes(n2, n3), b = host_pinvy ? pinvy_lds_bytes(r) : 0;
+  return a > b ? a : b;
+}
+
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g) {
   SliceArgs a;
+  a.npinv = (mode == SLICE_ITER && p.slice_pinvy) ? p.nb : 0;
+  a.pa = pinvy_args(p);
   a.zt = p.zt;
   a.gp = p.gp;
   a.wtab = p.wtab;
@@ -650,7 +673,7 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
   a.mode = mode;
   a.mixed = p.mixed;
   a.w_from_g = w_from_g;
-  const size_t lds = slice_lds_bytes(p.n2, p.n3);
+  const size_t lds = slice_launch_lds_bytes(p.n2, p.n3, p.r, a.npinv > 0);
   const int coop = coop_threads(p.n2, p.n3);
   if (coop > 0) {
     switch (p.n3) {
@@ -658,7 +681,7 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
   case n:                                                                                              \
     if constexpr (TubePlan<n>::M1 > 0) {                                                               \
       if (mode == SLICE_INIT) k_slice_coop<n, SLICE_INIT><<<p.n1, coop, lds, p.stream>>>(a);           \
-      else if (mode == SLICE_ITER) k_slice_coop<n, SLICE_ITER><<<p.n1, coop, lds, p.stream>>>(a);      \
+      else if (mode == SLICE_ITER) k_slice_coop<n, SLICE_ITER><<<p.n1 + a.npinv, coop, lds, p.stream>>>(a); \
       else if (mode == SLICE_RESULT) k_slice_coop<n, SLICE_RESULT><<<p.n1, coop, lds, p.stream>>>(a);  \
       else k_slice_coop<n, SLICE_KKT><<<p.n1, coop, lds, p.stream>>>(a);                               \
     }                                                                                                  \

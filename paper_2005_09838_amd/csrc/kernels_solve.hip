@@ -7,11 +7,13 @@
 //   two first-order recurrences over a contiguous chunk, and the chunks are joined by a
 //   log-depth scan of affine maps across the wavefront.
 //
-// k_ystep: per frequency, the Y-update (second line of eq. (updataXYW1)):
-//   G_X = X~^* H_rho1 X~ = X~^* X~ + rho1 (H X~)^*(H X~),  Y~ <- (I - eta P_X) Y~ + eta G_X^+ X~^* W~,
-//   with P_X = G_X^+ G_X; then the Gram of the new Y~ and the Fourier-domain H term of the
-//   objective.  FP64 throughout.
-// k_pinvy: the pseudo-inverse of that Gram and I - eta P_Y for the next X-update.
+// k_ystep: the Y-update (second line of eq. (updataXYW1)) over column blocks of each
+//   frequency: Y~ <- (I - eta P_X) Y~ + eta G_X^+ X~^* W~ with P_X = G_X^+ G_X, where
+//   G_X = X~^* H_rho1 X~ = X~^* X~ + rho1 (H X~)^*(H X~) and G_X^+ come from the X~^* W~
+//   launch; then each block's partial of the Gram of the new Y~.  FP64 arithmetic.
+// k_pinvy: G_Y from those partials, the Fourier-domain H term of the objective, the
+//   pseudo-inverse of G_Y and I - eta P_Y for the next X-update (the same work rides along
+//   the Z~ product in the iteration).
 #include "kernels.h"
 #include "pinv.h"
 
