@@ -11,7 +11,6 @@ struct Plan {
   int n1, n2, n3, r, nb;       // nb = n3/2 + 1 stored frequencies
   int nchunk, chunk;           // row chunks of the X~^* W~ reduction
   int ny, ycw;                 // column blocks of the Y-step per frequency, columns per block
-  int slice_pinvy;             // 1: the slice launch forms G_Y^+ in extra blocks (else the Z~ launch)
   double mu, rho1, rho2, eta;
   int mixed, force_eigen;
   hipStream_t stream;
@@ -60,8 +59,6 @@ void launch_zero(const Plan& p, void* dst, size_t bytes);
 // iteration
 enum SliceMode { SLICE_INIT = 0, SLICE_ITER = 1, SLICE_RESULT = 2, SLICE_KKT = 3 };
 bool slice_supported(int n3);
-bool slice_can_host_pinvy(int n1, int n2, int n3, int nb, int ncu);
-size_t slice_launch_lds_bytes(int n2, int n3, int r, int host_pinvy);
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g);
 void launch_zgemm(const Plan& p, int with_pinv = 0);   // with_pinv: also G_Y^+ (pinvy_block)
 void launch_agemm(const Plan& p, int raw_a = 0);

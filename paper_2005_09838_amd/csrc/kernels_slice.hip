@@ -20,8 +20,8 @@
 // entry, entirely in LDS:
 //   forward  y_j = (z_j + rho2 y_{j-1}) / alpha_j      (y = g on observed entries)
 //   backward w_j = y_j + rho2 / alpha_j * w_{j+1}       (w = g on observed entries)
+#include <type_traits>
 #include "kernels.h"
-#include "pinv.h"
 #include "tube_dft_gen.h"
 #include "tube_lds.h"
 
@@ -42,8 +42,6 @@ struct SliceArgs {
   float rho2;
   double mu, rho2d;
   int mode, mixed, w_from_g;
-  int npinv;     // SLICE_ITER: blocks n1 .. n1 + npinv - 1 form G_Y^+ of frequency blockIdx.x - n1
-  PinvyArgs pa;
 };
 
 template <int N>
@@ -401,24 +399,27 @@ __device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* 
 }
 
 // ---------------------------------------------------------------- cooperative slice kernel
-// The same three steps with T = M1 threads per tube (thread (t, j) = t * n2p + j, n2p = n2
+// The same three steps with T threads per tube (thread (t, j) = t * n2p + j, n2p = n2
 // rounded up to 64 so that every wave holds 64 consecutive tubes of one t).  The tube
-// transforms run through the tube's LDS row stage by stage; the W-step keeps one thread
-// per row.  Used when the block (T * n2p threads) fits 1024 threads.
+// transforms run through the tube's LDS row stage by stage.  T = M1 / 2 where that still
+// gives each thread at most two groups of every stage (else T = M1): the smaller blocks and
+// W-step segments of at most COOP_WS_L entries keep the registers low enough for three row
+// blocks per compute unit, so that a few hundred rows are all in flight at once and the
+// latency of one block's barriers and LDS round trips is hidden behind the others.  Used
+// when the block (T * n2p threads) fits 1024 threads.
+#define COOP_WS_L 8
+template <int N>
+__host__ __device__ constexpr int coop_tube_threads() {
+  constexpr int m1 = TubePlan<N>::M1, m2 = TubePlan<N>::M2;
+  return (m1 % 2 == 0 && m1 / 2 < m2 && m2 <= m1) ? m1 / 2 : m1;
+}
 template <int N, int MODE>
 __global__ void __launch_bounds__(1024) k_slice_coop(SliceArgs a) {
   using TL = TubeLds<N>;
-  constexpr int T = TL::M1, M1 = TL::M1, M2 = TL::M2, M = N / 2;
+  constexpr int T = coop_tube_threads<N>(), M1 = TL::M1, M2 = TL::M2, M = N / 2;
+  using FC = typename std::conditional<(T < M2), Fft4C2<M1, M2, T>, Fft4C<M1, M2>>::type;
   constexpr int LD = slice_ld<N>();
   extern __shared__ __align__(16) float smem[];
-  if constexpr (MODE == SLICE_ITER) {
-    // blocks past the last row: G_Y^+ and I - eta P_Y for the next X-step (pinvy_block),
-    // dispatched after every row block, into the last, partly idle round of row blocks
-    if ((int)blockIdx.x >= a.n1) {
-      pinvy_block((int)blockIdx.x - a.n1, a.pa, (unsigned char*)smem);
-      return;
-    }
-  }
   const int n2 = a.n2, nwr = (n2 + 31) >> 5, n2p = (n2 + 63) & ~63;
   float* zs = smem;                                   // [n2][LD]
   float* tab = zs + (size_t)n2 * LD;                  // [4][n2]
@@ -448,7 +449,7 @@ __global__ void __launch_bounds__(1024) k_slice_coop(SliceArgs a) {
     __syncthreads();
     if (act) fft4_step_a<M1, M2, -1>(row, twm, t, T);
     __syncthreads();
-    Fft4C<M1, M2> sc;
+    FC sc;
     if (act) sc.read(row, t);
     __syncthreads();
     if (act) sc.template write<-1>(row, t);
@@ -492,15 +493,15 @@ __global__ void __launch_bounds__(1024) k_slice_coop(SliceArgs a) {
   if (thomas) {
     int S = 1;
     while (S < 64 && 2 * S * N <= nt) S <<= 1;
-    while ((n2 + S - 1) / S > 16) S <<= 1;   // segment length within the register budget
+    while ((n2 + S - 1) / S > COOP_WS_L) S <<= 1;   // segment length within the register budget
     switch (S) {   // the segment count is a compile-time constant of the shuffles
-      case 1: wstep_segmented<16, 1>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      case 2: wstep_segmented<16, 2>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      case 4: wstep_segmented<16, 4>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      case 8: wstep_segmented<16, 8>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      case 16: wstep_segmented<16, 16>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      case 32: wstep_segmented<16, 32>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      default: wstep_segmented<16, 64>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 1: wstep_segmented<COOP_WS_L, 1>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 2: wstep_segmented<COOP_WS_L, 2>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 4: wstep_segmented<COOP_WS_L, 4>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 8: wstep_segmented<COOP_WS_L, 8>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 16: wstep_segmented<COOP_WS_L, 16>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      case 32: wstep_segmented<COOP_WS_L, 32>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+      default: wstep_segmented<COOP_WS_L, 64>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
     }
   }
   __syncthreads();
@@ -556,7 +557,7 @@ __global__ void __launch_bounds__(1024) k_slice_coop(SliceArgs a) {
     __syncthreads();   // the transform below overwrites the rows
     if (act) fft4_step_a<M1, M2, +1>(row, twm, t, T);
     __syncthreads();
-    Fft4C<M1, M2> sc;
+    FC sc;
     if (act) sc.read(row, t);
     __syncthreads();
     if (act) sc.template write<+1>(row, t);
@@ -611,7 +612,7 @@ size_t slice_lds_bytes(int n2, int n3) {
 static int coop_threads(int n2, int n3) {
   int m1 = 0;
   switch (n3) {
-#define TCTF_CASE(n) case n: m1 = TubePlan<n>::M1; break;
+#define TCTF_CASE(n) case n: m1 = TubePlan<n>::M1 > 0 ? coop_tube_threads<n>() : 0; break;
     TUBE_DFT_SIZES(TCTF_CASE)
 #undef TCTF_CASE
     default: break;
@@ -642,20 +643,8 @@ void slice_set_attr(int n3, size_t lds) {
   }
 }
 
-bool slice_can_host_pinvy(int n1, int n2, int n3, int nb, int ncu) {
-  const int rem = ncu > 0 ? n1 % ncu : 0;
-  return coop_threads(n2, n3) > 0 && rem > 0 && rem + nb <= ncu;
-}
-
-size_t slice_launch_lds_bytes(int n2, int n3, int r, int host_pinvy) {
-  const size_t a = slice_lds_bytes(n2, n3), b = host_pinvy ? pinvy_lds_bytes(r) : 0;
-  return a > b ? a : b;
-}
-
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g) {
   SliceArgs a;
-  a.npinv = (mode == SLICE_ITER && p.slice_pinvy) ? p.nb : 0;
-  a.pa = pinvy_args(p);
   a.zt = p.zt;
   a.gp = p.gp;
   a.wtab = p.wtab;
@@ -673,7 +662,7 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
   a.mode = mode;
   a.mixed = p.mixed;
   a.w_from_g = w_from_g;
-  const size_t lds = slice_launch_lds_bytes(p.n2, p.n3, p.r, a.npinv > 0);
+  const size_t lds = slice_lds_bytes(p.n2, p.n3);
   const int coop = coop_threads(p.n2, p.n3);
   if (coop > 0) {
     switch (p.n3) {
@@ -681,7 +670,7 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
   case n:                                                                                              \
     if constexpr (TubePlan<n>::M1 > 0) {                                                               \
       if (mode == SLICE_INIT) k_slice_coop<n, SLICE_INIT><<<p.n1, coop, lds, p.stream>>>(a);           \
-      else if (mode == SLICE_ITER) k_slice_coop<n, SLICE_ITER><<<p.n1 + a.npinv, coop, lds, p.stream>>>(a); \
+      else if (mode == SLICE_ITER) k_slice_coop<n, SLICE_ITER><<<p.n1, coop, lds, p.stream>>>(a); \
       else if (mode == SLICE_RESULT) k_slice_coop<n, SLICE_RESULT><<<p.n1, coop, lds, p.stream>>>(a);  \
       else k_slice_coop<n, SLICE_KKT><<<p.n1, coop, lds, p.stream>>>(a);                               \
     }                                                                                                  \

@@ -268,6 +268,41 @@ struct Fft4C {
   }
 };
 
+// Fft4C with the groups t and t + T of each thread (T < M2 <= 2 T).
+template <int M1, int M2, int T>
+struct Fft4C2 {
+  static_assert(T < M2 && M2 <= 2 * T, "two groups per thread");
+  float re[2][M1], im[2][M1];
+  __device__ __forceinline__ void read(const float* row, int t) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = t + h * T;
+      if (g < M2) {
+#pragma unroll
+        for (int n1 = 0; n1 < M1; ++n1) {
+          re[h][n1] = row[2 * (n1 + M1 * g)];
+          im[h][n1] = row[2 * (n1 + M1 * g) + 1];
+        }
+      }
+    }
+  }
+  template <int S>
+  __device__ __forceinline__ void write(float* row, int t) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = t + h * T;
+      if (g < M2) {
+        dftc<M1, S>(re[h], im[h]);
+#pragma unroll
+        for (int k1 = 0; k1 < M1; ++k1) {
+          row[2 * (g + M2 * k1)] = re[h][k1];
+          row[2 * (g + M2 * k1) + 1] = im[h][k1];
+        }
+      }
+    }
+  }
+};
+
 // post-step of the forward transform with C in natural order, pairs b = t, t + T, ...
 template <int N, class Store>
 __device__ __forceinline__ void tube_fwd_post_nat(const float* row, const float2* __restrict__ twn, int t, int T,
