@@ -261,7 +261,7 @@ static tctf_status enqueue_iteration(tctf_ctx* c) {
   if (s == TCTF_OK) s = stage(c, 5, [&] { tctf::launch_ystep(p, 0); });
   // Z~ = X~Y~; G_Y^+ and I - eta P_Y for the next X-step ride along in extra blocks of this
   // launch or, when its last round of row blocks has room for them, of the slice launch
-  if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p, 1); });
+  if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p, tctf::slice_hosts_pinvy(p.n2, p.n3) ? 0 : 1); });
   if (s == TCTF_OK) s = stage(c, 0, [&] { tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0); });
   if (s != TCTF_OK) return s;
   return check_launch();
@@ -293,7 +293,7 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   }
   fill_plan(c, (hipStream_t)hip_stream);
   const Plan& p = c->plan;
-  tctf::slice_set_attr(p.n3, tctf::slice_lds_bytes(p.n2, p.n3));
+  tctf::slice_set_attr(p.n3, tctf::slice_launch_lds_bytes(p.n2, p.n3, p.r));
   tctf::ystep_set_attr(tctf::ystep_lds_bytes(p.r, p.ycw));
   tctf::bgemm_set_attr(tctf::bgemm_lds_bytes(p.r, p.chunk));
   tctf::pinvy_set_attr(p.r);

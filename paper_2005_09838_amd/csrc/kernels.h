@@ -59,6 +59,8 @@ void launch_zero(const Plan& p, void* dst, size_t bytes);
 // iteration
 enum SliceMode { SLICE_INIT = 0, SLICE_ITER = 1, SLICE_RESULT = 2, SLICE_KKT = 3 };
 bool slice_supported(int n3);
+bool slice_hosts_pinvy(int n2, int n3);   // the iteration's slice launch also forms G_Y^+
+size_t slice_launch_lds_bytes(int n2, int n3, int r);
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g);
 void launch_zgemm(const Plan& p, int with_pinv = 0);   // with_pinv: also G_Y^+ (pinvy_block)
 void launch_agemm(const Plan& p, int raw_a = 0);

@@ -22,6 +22,7 @@
 //   backward w_j = y_j + rho2 / alpha_j * w_{j+1}       (w = g on observed entries)
 #include <type_traits>
 #include "kernels.h"
+#include "pinv.h"
 #include "tube_dft_gen.h"
 #include "tube_lds.h"
 
@@ -42,6 +43,8 @@ struct SliceArgs {
   float rho2;
   double mu, rho2d;
   int mode, mixed, w_from_g;
+  int npinv;     // SLICE_ITER: blocks n1 .. n1 + npinv - 1 form G_Y^+ of frequency blockIdx.x - n1
+  PinvyArgs pa;
 };
 
 template <int N>
@@ -405,8 +408,10 @@ __device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* 
 // gives each thread at most two groups of every stage (else T = M1): the smaller blocks and
 // W-step segments of at most COOP_WS_L entries keep the registers low enough for three row
 // blocks per compute unit, so that a few hundred rows are all in flight at once and the
-// latency of one block's barriers and LDS round trips is hidden behind the others.  Used
-// when the block (T * n2p threads) fits 1024 threads.
+// latency of one block's barriers and LDS round trips is hidden behind the others.  In an
+// iteration, nb more blocks after the rows form G_Y^+ and I - eta P_Y for the next X-step
+// (pinvy_block); the register cap keeps their allocation from raising the row blocks'.
+// Used when the block (T * n2p threads) fits 1024 threads.
 #define COOP_WS_L 8
 template <int N>
 __host__ __device__ constexpr int coop_tube_threads() {
@@ -414,12 +419,18 @@ __host__ __device__ constexpr int coop_tube_threads() {
   return (m1 % 2 == 0 && m1 / 2 < m2 && m2 <= m1) ? m1 / 2 : m1;
 }
 template <int N, int MODE>
-__global__ void __launch_bounds__(1024) k_slice_coop(SliceArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) k_slice_coop(SliceArgs a) {
   using TL = TubeLds<N>;
   constexpr int T = coop_tube_threads<N>(), M1 = TL::M1, M2 = TL::M2, M = N / 2;
   using FC = typename std::conditional<(T < M2), Fft4C2<M1, M2, T>, Fft4C<M1, M2>>::type;
   constexpr int LD = slice_ld<N>();
   extern __shared__ __align__(16) float smem[];
+  if constexpr (MODE == SLICE_ITER) {
+    if ((int)blockIdx.x >= a.n1) {
+      pinvy_block((int)blockIdx.x - a.n1, a.pa, (unsigned char*)smem);
+      return;
+    }
+  }
   const int n2 = a.n2, nwr = (n2 + 31) >> 5, n2p = (n2 + 63) & ~63;
   float* zs = smem;                                   // [n2][LD]
   float* tab = zs + (size_t)n2 * LD;                  // [4][n2]
@@ -643,8 +654,17 @@ void slice_set_attr(int n3, size_t lds) {
   }
 }
 
+bool slice_hosts_pinvy(int n2, int n3) { return coop_threads(n2, n3) > 0; }
+
+size_t slice_launch_lds_bytes(int n2, int n3, int r) {
+  const size_t a = slice_lds_bytes(n2, n3), b = slice_hosts_pinvy(n2, n3) ? pinvy_lds_bytes(r) : 0;
+  return a > b ? a : b;
+}
+
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g) {
   SliceArgs a;
+  a.npinv = (mode == SLICE_ITER && slice_hosts_pinvy(p.n2, p.n3)) ? p.nb : 0;
+  a.pa = pinvy_args(p);
   a.zt = p.zt;
   a.gp = p.gp;
   a.wtab = p.wtab;
@@ -662,7 +682,7 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
   a.mode = mode;
   a.mixed = p.mixed;
   a.w_from_g = w_from_g;
-  const size_t lds = slice_lds_bytes(p.n2, p.n3);
+  const size_t lds = slice_launch_lds_bytes(p.n2, p.n3, p.r);
   const int coop = coop_threads(p.n2, p.n3);
   if (coop > 0) {
     switch (p.n3) {
@@ -670,7 +690,7 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
   case n:                                                                                              \
     if constexpr (TubePlan<n>::M1 > 0) {                                                               \
       if (mode == SLICE_INIT) k_slice_coop<n, SLICE_INIT><<<p.n1, coop, lds, p.stream>>>(a);           \
-      else if (mode == SLICE_ITER) k_slice_coop<n, SLICE_ITER><<<p.n1, coop, lds, p.stream>>>(a); \
+      else if (mode == SLICE_ITER) k_slice_coop<n, SLICE_ITER><<<p.n1 + a.npinv, coop, lds, p.stream>>>(a); \
       else if (mode == SLICE_RESULT) k_slice_coop<n, SLICE_RESULT><<<p.n1, coop, lds, p.stream>>>(a);  \
       else k_slice_coop<n, SLICE_KKT><<<p.n1, coop, lds, p.stream>>>(a);                               \
     }                                                                                                  \
