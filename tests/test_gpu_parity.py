@@ -44,6 +44,11 @@ def test_smallest_workload_50_iterations():
     (48, 40, 6, 20, 0.7),     # r > 16: the largest rank bucket of the products and pivots
     (1100, 9, 4, 2, 0.5),     # n1 > 1024: the column-in-LDS H solve
     (300, 12, 6, 3, 0.4),     # n1 past one round of compute units, two row groups of G_X
+    (20, 30, 24, 3, 0.4),     # tube transforms with two step-C groups per thread: 24 = 2 (4 x 3),
+    (24, 70, 32, 4, 0.5),     # 32 = 2 (4 x 4),
+    (18, 40, 48, 3, 0.4),     # 48 = 2 (6 x 4),
+    (16, 20, 96, 4, 0.5),     # 96 = 2 (8 x 6)
+    (12, 130, 128, 5, 0.4),   # and 128 = 2 (8 x 8) with n2 past two 64-column groups
 ])
 def test_ragged_shapes(n1, n2, n3, r, p):
     d = make_inputs(n1, n2, n3, r, p=p, seed=n1 + n2 + n3, weekly=True, sigma_od=1.0, noise=0.02)
