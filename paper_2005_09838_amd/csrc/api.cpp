@@ -259,8 +259,8 @@ static tctf_status enqueue_iteration(tctf_ctx* c) {
   if (s == TCTF_OK) s = stage(c, 3, [&] { tctf::launch_hsolve(p); });
   if (s == TCTF_OK) s = stage(c, 4, [&] { tctf::launch_bgemm(p); });
   if (s == TCTF_OK) s = stage(c, 5, [&] { tctf::launch_ystep(p, 0); });
-  // Z~ = X~Y~; G_Y^+ and I - eta P_Y for the next X-step ride along in extra blocks of this
-  // launch or, when its last round of row blocks has room for them, of the slice launch
+  // Z~ = X~Y~; G_Y^+ and I - eta P_Y for the next X-step ride along in extra blocks of the
+  // cooperative slice launch, or of this launch where the slice runs the per-thread kernel
   if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p, tctf::slice_hosts_pinvy(p.n2, p.n3) ? 0 : 1); });
   if (s == TCTF_OK) s = stage(c, 0, [&] { tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0); });
   if (s != TCTF_OK) return s;
