@@ -471,30 +471,38 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
   double fit = 0.0, ridge = 0.0, sm = 0.0;
   {
     constexpr float inv_m = 1.0f / M;
+    constexpr int B = 4;   // G entries loaded ahead of their use: one load latency per four
     const int jw0 = (j - lane) >> 5;
     float facc = 0.0f;
-    for (int q = t; q < N; q += T) {
-      float zq = 0.0f, gv = 0.0f;
-      if (act) {
-        zq = need_z ? row[q] * inv_m : 0.0f;
-        gv = gtube[q];
+    for (int q0 = t; q0 < N; q0 += B * T) {
+      float gb[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int q = q0 + u * T;
+        gb[u] = ld_or(gtube, (size_t)q, act && q < N, 0.0f);
       }
-      const bool obs = act && !is_unobserved(gv);
-      float wv, d;
-      if (!thomas) {
-        wv = obs ? gv : 0.0f;
-        d = zq - wv;
-      } else {
-        wv = obs ? gv : zq;
-        d = obs ? zq - gv : 0.0f;
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int q = q0 + u * T;
+        if (q >= N) break;   // the same in the whole wavefront (one t per wavefront)
+        const float zq = (act && need_z) ? row[q] * inv_m : 0.0f, gv = gb[u];
+        const bool obs = act && !is_unobserved(gv);
+        float wv, d;
+        if (!thomas) {
+          wv = obs ? gv : 0.0f;
+          d = zq - wv;
+        } else {
+          wv = obs ? gv : zq;
+          d = obs ? zq - gv : 0.0f;
+        }
+        if (act) {
+          facc = fmaf(d, d, facc);
+          row[q] = wv;
+          if (a.z_out) a.z_out[(i * n2 + j) * N + q] = zq;
+        }
+        const uint64_t bal = __ballot(obs);
+        if (lane < 2 && jw0 + lane < nwr) obits[q * nwr + jw0 + lane] = (uint32_t)(bal >> (32 * lane));
       }
-      if (act) {
-        facc = fmaf(d, d, facc);
-        row[q] = wv;
-        if (a.z_out) a.z_out[(i * n2 + j) * N + q] = zq;
-      }
-      const uint64_t bal = __ballot(obs);
-      if (lane < 2 && jw0 + lane < nwr) obits[q * nwr + jw0 + lane] = (uint32_t)(bal >> (32 * lane));
     }
     fit += (double)facc;
   }

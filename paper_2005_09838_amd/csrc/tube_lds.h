@@ -192,25 +192,40 @@ __device__ __forceinline__ void fft4_step_c(float* row, int t, int T) {
   }
 }
 
-// pre-step of the inverse for the pairs b = t, t + T, ... <= M/2 (see tube_inv_lds)
+// pre-step of the inverse for the pairs b = t, t + T, ... <= M/2 (see tube_inv_lds); the
+// bins of four pairs are loaded (from clamped addresses, unconditionally) before any of them
+// is used, so a thread waits for one load latency per four pairs rather than per pair
 template <int N>
 __device__ __forceinline__ void tube_inv_pre(const float2* __restrict__ src, size_t stride, float* row,
                                              const float2* __restrict__ twn, int t, int T) {
-  constexpr int M = N / 2;
-  for (int b = t; b <= M / 2; b += T) {
-    const int mb = M - b;
-    const float2 xb = src[(size_t)b * stride], xm = src[(size_t)mb * stride];
-    const float xbr = xb.x, xbi = (b == 0) ? 0.0f : xb.y;
-    const float xmr = xm.x, xmi = (b == 0) ? 0.0f : xm.y;
-    const float er = 0.5f * (xbr + xmr), ei = 0.5f * (xbi - xmi);
-    const float dr = 0.5f * (xbr - xmr), di = 0.5f * (xbi + xmi);
-    const float2 w = twn[b];
-    const float orr = fmaf(dr, w.x, di * w.y), oi = fmaf(di, w.x, -dr * w.y);
-    row[2 * b] = er - oi;
-    row[2 * b + 1] = ei + orr;
-    if (b != 0 && mb != b) {
-      row[2 * mb] = er + oi;
-      row[2 * mb + 1] = orr - ei;
+  constexpr int M = N / 2, B = 4;
+  for (int b0 = t; b0 <= M / 2; b0 += B * T) {
+    float2 xbv[B], xmv[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int b = b0 + u * T;
+      const bool ok = b <= M / 2;
+      xbv[u] = src[(size_t)(ok ? b : 0) * stride];
+      xmv[u] = src[(size_t)(ok ? M - b : 0) * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int b = b0 + u * T;
+      if (b > M / 2) break;
+      const int mb = M - b;
+      const float2 xb = xbv[u], xm = xmv[u];
+      const float xbr = xb.x, xbi = (b == 0) ? 0.0f : xb.y;
+      const float xmr = xm.x, xmi = (b == 0) ? 0.0f : xm.y;
+      const float er = 0.5f * (xbr + xmr), ei = 0.5f * (xbi - xmi);
+      const float dr = 0.5f * (xbr - xmr), di = 0.5f * (xbi + xmi);
+      const float2 w = twn[b];
+      const float orr = fmaf(dr, w.x, di * w.y), oi = fmaf(di, w.x, -dr * w.y);
+      row[2 * b] = er - oi;
+      row[2 * b + 1] = ei + orr;
+      if (b != 0 && mb != b) {
+        row[2 * mb] = er + oi;
+        row[2 * mb + 1] = orr - ei;
+      }
     }
   }
 }
