@@ -471,7 +471,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
   double fit = 0.0, ridge = 0.0, sm = 0.0;
   {
     constexpr float inv_m = 1.0f / M;
-    constexpr int B = 4;   // G entries loaded ahead of their use: one load latency per four
+    constexpr int B = 7;   // G entries loaded ahead of their use: one load latency per seven
     const int jw0 = (j - lane) >> 5;
     float facc = 0.0f;
     for (int q0 = t; q0 < N; q0 += B * T) {

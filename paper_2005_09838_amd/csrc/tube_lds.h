@@ -198,7 +198,7 @@ __device__ __forceinline__ void fft4_step_c(float* row, int t, int T) {
 template <int N>
 __device__ __forceinline__ void tube_inv_pre(const float2* __restrict__ src, size_t stride, float* row,
                                              const float2* __restrict__ twn, int t, int T) {
-  constexpr int M = N / 2, B = 4;
+  constexpr int M = N / 2, B = 8;
   for (int b0 = t; b0 <= M / 2; b0 += B * T) {
     float2 xbv[B], xmv[B];
 #pragma unroll
