@@ -32,6 +32,9 @@ def _pins():
         lambda: PG.test_objective_never_increases(1.0, 4),
         lambda: PG.test_unregularised_iteration_is_alternating_least_squares(),
         lambda: PG.test_exact_recovery_in_one_sweep(),
+        lambda: PG.test_termination_on_planted_differences(),
+        lambda: PG.test_stationarity_normalisation_against_spatial_gradient(4),
+        lambda: PG.test_stationarity_normalisation_against_spatial_gradient(5),
     ]
 
 
@@ -91,6 +94,30 @@ def _tprod_transposed(a, b):
     return T.idft3(np.einsum("irk,rjk->ijk", at, bt[:, :, ::-1])).real
 
 
+def _termination_real_parts(prev, cur):
+    return (float(np.abs((cur.xt - prev.xt).real).max()), float(np.abs((cur.yt - prev.yt).real).max()),
+            float(np.linalg.norm(cur.w - prev.w)))
+
+
+def _termination_w_sup_norm(prev, cur):
+    return (float(np.abs(cur.xt - prev.xt).max()), float(np.abs(cur.yt - prev.yt).max()),
+            float(np.abs(cur.w - prev.w).max()))
+
+
+def _stationarity_variant(half_spectrum=False, spatial_w=False):
+    def stat(prob, st):
+        m3 = prob.shape[2]
+        s = 0.0
+        for k in range(m3 // 2 + 1 if half_spectrum else m3):   # half spectrum: bin weights dropped
+            gx = A.grad_x(st.xt[:, :, k], st.yt[:, :, k], st.wt[:, :, k], prob.hth, prob.rho1)
+            gy = A.grad_y(st.xt[:, :, k], st.yt[:, :, k], st.wt[:, :, k], prob.hth, prob.rho1)
+            s += np.sum(np.abs(gx) ** 2) + np.sum(np.abs(gy) ** 2)
+        wn = np.linalg.norm(st.w) if spatial_w else np.linalg.norm(st.wt)
+        denom = wn * (np.linalg.norm(st.xt) + np.linalg.norm(st.yt))
+        return {"factor": float(np.sqrt(s) / denom), "w_kkt": 0.0, "w_obs": 0.0}
+    return stat
+
+
 MUTANTS = {
     "grad_x drops the rho1 term": [(A, "grad_x", _grad_x_no_rho1)],
     "grad_y sign of W flipped": [(A, "grad_y", _grad_y_wrong_sign)],
@@ -104,6 +131,16 @@ MUTANTS = {
                                         (O, "objective_spatial", _objective_half_missing),
                                         (A, "objective_spatial", _objective_half_missing)],
     "t-product with reversed bins": [(T, "tprod", _tprod_transposed), (O, "tprod", _tprod_transposed)],
+    "termination takes the largest real part": [(A, "termination", _termination_real_parts),
+                                                (O, "termination", _termination_real_parts)],
+    "termination measures W in the sup norm": [(A, "termination", _termination_w_sup_norm),
+                                               (O, "termination", _termination_w_sup_norm)],
+    "stationarity over the half spectrum without bin weights": [
+        (A, "stationarity", _stationarity_variant(half_spectrum=True)),
+        (O, "stationarity", _stationarity_variant(half_spectrum=True))],
+    "stationarity normalised by the spatial ||W||": [
+        (A, "stationarity", _stationarity_variant(spatial_w=True)),
+        (O, "stationarity", _stationarity_variant(spatial_w=True))],
 }
 
 
