@@ -11,6 +11,8 @@ import oracle as O
 import oracle.algorithm as A
 import oracle.model as M
 import oracle.tensor_algebra as T
+import oracle.adjoint as AD
+from tests import test_oracle_adjoint as PD
 from tests import test_oracle_algebra as PA
 from tests import test_oracle_algorithm as PG
 from tests import test_oracle_model as PM
@@ -35,6 +37,9 @@ def _pins():
         lambda: PG.test_termination_on_planted_differences(),
         lambda: PG.test_stationarity_normalisation_against_spatial_gradient(4),
         lambda: PG.test_stationarity_normalisation_against_spatial_gradient(5),
+        lambda: PD.test_one_iteration_adjoint_matches_finite_differences(0.7, 2),
+        lambda: PD.test_unrolled_hypergradients_match_central_differences(1.0),
+        lambda: PD.test_w_step_adjoint_without_rho2_is_a_scaling(),
     ]
 
 
@@ -118,6 +123,25 @@ def _stationarity_variant(half_spectrum=False, spatial_w=False):
     return stat
 
 
+def _transpose_without_conjugate(a):
+    return np.swapaxes(a, -1, -2)
+
+
+def _w_step_adjoint_no_rho2(prob, w_new, w_bar, theta_bar):
+    saved = theta_bar.rho2
+    out = _W_STEP_ADJOINT(prob, w_new, w_bar, theta_bar)
+    theta_bar.rho2 = saved
+    return out
+
+
+def _heldout_grad_unnormalised(w, m, hold):
+    h = hold.astype(bool)
+    e = np.where(h, w - m, 0.0)
+    return e / np.linalg.norm(e)
+
+
+_W_STEP_ADJOINT = AD.w_step_adjoint
+
 MUTANTS = {
     "grad_x drops the rho1 term": [(A, "grad_x", _grad_x_no_rho1)],
     "grad_y sign of W flipped": [(A, "grad_y", _grad_y_wrong_sign)],
@@ -138,6 +162,9 @@ MUTANTS = {
     "stationarity over the half spectrum without bin weights": [
         (A, "stationarity", _stationarity_variant(half_spectrum=True)),
         (O, "stationarity", _stationarity_variant(half_spectrum=True))],
+    "adjoint products without the conjugate": [(AD, "_h", _transpose_without_conjugate)],
+    "W-step adjoint drops the rho2 weight's term": [(AD, "w_step_adjoint", _w_step_adjoint_no_rho2)],
+    "held-out error gradient without 1 / ||P_H(M)||": [(AD, "heldout_rse_grad", _heldout_grad_unnormalised)],
     "stationarity normalised by the spatial ||W||": [
         (A, "stationarity", _stationarity_variant(spatial_w=True)),
         (O, "stationarity", _stationarity_variant(spatial_w=True))],
