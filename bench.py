@@ -51,13 +51,16 @@ def algorithmic_bytes(n1, n2, n3, r, mixed):
 
 
 def stage_bytes(stage, n1, n2, n3, r, mixed):
-    """Algorithmic bytes of one launch of each stage (what the kernel must read and write)."""
+    """Algorithmic bytes of one launch of each stage: the kernel's share of the fused
+    iteration's minimum traffic.  The slice kernel's share is the G read and the W~ write
+    only: in the fused iteration Z~ never reaches memory (it is formed on chip from the
+    factors), so the Z~ round trip it still makes is not counted as useful traffic."""
     nb = n3 // 2 + 1
     nh = n1 * n2 * nb
     sw = 4 if mixed else 8
     fx, fy = 8 * nb * r * n1, 8 * nb * r * n2
     return {
-        "slice": 8 * nh + 4 * n1 * n2 * n3 + sw * nh,   # read Z~ and G, write W~
+        "slice": 4 * n1 * n2 * n3 + sw * nh,             # read G, write W~
         "zgemm": fx + fy + 8 * nh,                       # read X~, Y~, write Z~
         "agemm": sw * nh + fy + fx + fx,                 # read W~, Y~, X~, write the X right-hand side
         "hsolve": 2 * fx,                                # read the right-hand side, write X~
@@ -74,31 +77,41 @@ STAGE_KERNELS = {"slice": "k_slice_coop", "zgemm": "k_zgemm", "agemm": "k_agemm"
 
 
 def run_precision(prec, d, w, steps, warmup, dev, torch):
-    """Warm up; time every stage over 20 iterations (to pick the dominant one); time `steps`
-    iterations as the library runs them (graph replays); then `steps` more with only the
-    dominant stage's launches bracketed by HIP events on the library's stream (event
+    """Warm up (the first step call captures the iteration graph, so capture stays outside
+    every timed region); time `steps` iterations as the library runs them (graph replays) on
+    the wall clock between two synchronisations; time five more blocks of `steps` iterations
+    with HIP events on the library's stream (torch's current stream) and keep their median;
+    then time every stage over 20 iterations (to pick the dominant one) and `steps` more
+    iterations with only the dominant stage's launches bracketed by HIP events (event
     recording makes those launches eager, which changes the gaps between kernels, not the
     kernels)."""
     from paper_2005_09838_amd import Completion
     t = lambda a: torch.from_numpy(a).to(dev)
     c = Completion(t(d["G"]), t(d["omega"]), w.r, mu=w.mu, rho1=w.rho1, rho2=w.rho2, precision=prec,
                    X0=t(d["X0"]), Y0=t(d["Y0"]))
-    c.step(warmup)
-    c.profile(STAGE_NAMES)
-    c.step(20)
-    stages = {name: us for name, (us, n) in c.profile_read().items() if n}
-    dominant = max(stages, key=stages.get)
-    c.profile([])
+    c.step(max(warmup, 1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     c.step(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    blocks = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c.step(steps)
+        e1.record()
+        e1.synchronize()
+        blocks.append(e0.elapsed_time(e1) / steps)
+    c.profile(STAGE_NAMES)
+    c.step(20)
+    stages = {name: us for name, (us, n) in c.profile_read().items() if n}
+    dominant = max(stages, key=stages.get)
     c.profile([dominant])
     c.step(steps)
     live_us, launches = c.profile_read()[dominant]
     c.profile([])
-    return c, dt, stages, dominant, live_us, launches
+    return c, dt, sorted(blocks), stages, dominant, live_us, launches
 
 
 def measured_traffic(stage, prec):
@@ -206,23 +219,57 @@ def rse_history(prec, d, w, iters, every, dev, torch, M):
     return hist
 
 
-def cpu_baseline(d, w, iters):
-    """The FP64 oracle on the host, single-threaded and with all cores, for `iters` iterations."""
-    import numpy as np  # noqa: F401
+def host_cpu():
+    """Model name and logical core count of the host (for the CPU baseline's context)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def cpu_baseline(d, w, iters, iters_all):
+    """The FP64 oracle on the host: `iters` iterations on one BLAS thread (their final state
+    is the reference of the error statements) and `iters_all` with every core the process
+    may use."""
     import oracle
     from threadpoolctl import threadpool_limits
 
     out = {}
-    for label, threads in (("one_core", 1), ("all_cores", min(16, os.cpu_count() or 1))):
+    cores = host_cpu()["affinity"] or os.cpu_count() or 1
+    for label, threads, n in (("one_core", 1, iters), ("all_cores", cores, iters_all)):
+        if n <= 0:
+            continue
         with threadpool_limits(limits=threads):
             prob = oracle.Problem(d["G"], d["omega"], w.r, w.mu, w.rho1, w.rho2)
             st = oracle.initial_state(prob, d["X0"], d["Y0"])
             t0 = time.perf_counter()
-            for _ in range(iters):
+            for _ in range(n):
                 st = oracle.iterate(prob, st)
             dt = time.perf_counter() - t0
-        out[label] = {"iters_per_s": iters / dt, "cores": threads, "seconds": dt, "state": st}
+        out[label] = {"iters_per_s": n / dt, "cores": threads, "seconds": dt, "iters": n, "state": st}
     return out
+
+
+def elementwise_error(a, ref):
+    """Relative Frobenius error, max error relative to max |ref|, and the worst per-OD-row
+    relative error of a against ref (arrays [n1][n2][n3])."""
+    import numpy as np
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = (a - ref).reshape(ref.shape[0], -1)
+    rn = np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
+    dn = np.linalg.norm(d, axis=1)
+    rowrel = np.where(dn == 0.0, 0.0, dn / np.maximum(rn, 1e-30))
+    return {"fro": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "max": float(np.abs(d).max() / np.abs(ref).max()),
+            "worst_row": float(rowrel.max())}
 
 
 def main():
@@ -231,7 +278,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rse-iters", type=int, default=200)
-    ap.add_argument("--oracle-iters", type=int, default=2)
+    ap.add_argument("--oracle-iters", type=int, default=50,
+                    help="FP64 oracle iterations (one core): CPU baseline and error statements")
+    ap.add_argument("--oracle-iters-all-cores", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT")
@@ -261,8 +310,8 @@ def main():
     res = {}
     precs = (args.only,) if args.only else ("fp32", "mixed")
     for prec in precs:
-        c, dt, stages, dominant, live_us, launches = run_precision(prec, d, w, args.steps, args.warmup, dev,
-                                                                   torch)
+        c, dt, blocks, stages, dominant, live_us, launches = run_precision(prec, d, w, args.steps, args.warmup,
+                                                                           dev, torch)
         mixed = prec == "mixed"
         ips = args.steps / dt
         W = c.result()["W"]
@@ -270,6 +319,9 @@ def main():
         res[prec] = {
             "iters_per_s": ips,
             "ms_per_step": 1000.0 * dt / args.steps,
+            "ms_per_step_events_median_of_5": blocks[2],
+            "ms_per_step_events_blocks": [round(b, 5) for b in blocks],
+            "hbm_frac_whole_iteration": algorithmic_bytes(n1, n2, n3, r, mixed) * ips / 1e9 / PEAK_HBM_GBPS,
             "hbm_gbps_algorithmic": algorithmic_bytes(n1, n2, n3, r, mixed) * ips / 1e9,
             "stage_us": {k: round(v, 3) for k, v in stages.items()},
             "dominant_kernel": dominant,
@@ -278,7 +330,7 @@ def main():
             "stage_gbps": {k: round(stage_bytes(k, n1, n2, n3, r, mixed) / (v * 1e-6) / 1e9, 1)
                            for k, v in stages.items()},
             "rse_after_timed_run": rse_end,
-            "iterations_at_rse": args.warmup + 20 + 2 * args.steps,
+            "iterations_at_rse": max(args.warmup, 1) + 20 + 7 * args.steps,
         }
         c.close()
 
@@ -300,10 +352,11 @@ def main():
             it = args.rse_iters if prec == "fp32" else t_equal
             res[prec]["seconds_to_fp32_rse"] = None if it is None else it / res[prec]["iters_per_s"]
 
-    # error against the FP64 oracle after the oracle's sample, and the CPU baseline
+    # the CPU baseline (the FP64 oracle timed on the host) and the error of both precisions
+    # against its state after the same number of iterations (element-wise and per OD row)
     cpu = None
     if not args.no_cpu and args.oracle_iters > 0:
-        base = cpu_baseline(d, w, args.oracle_iters)
+        base = cpu_baseline(d, w, args.oracle_iters, args.oracle_iters_all_cores)
         st = base["one_core"]["state"]
         for prec in precs:
             from paper_2005_09838_amd import Completion
@@ -311,13 +364,19 @@ def main():
             c = Completion(t(d["G"]), t(d["omega"]), r, mu=w.mu, rho1=w.rho1, rho2=w.rho2, precision=prec,
                            X0=t(d["X0"]), Y0=t(d["Y0"]))
             c.step(args.oracle_iters)
-            Wg = c.result()["W"].cpu().numpy().astype(np.float64)
+            Wg = c.result()["W"].cpu().numpy()
             c.close()
-            res[prec][f"rel_err_vs_fp64_oracle_after_{args.oracle_iters}_iters"] = float(
-                np.linalg.norm(Wg - st.w) / np.linalg.norm(st.w))
-        cpu = {"value": base["one_core"]["iters_per_s"], "unit": "iters/s", "cores": 1, "kind": "oracle",
-               "sample": f"{args.oracle_iters} iterations of the FP64 NumPy oracle at {WORKLOAD} (single BLAS thread)",
-               "all_cores": {"value": base["all_cores"]["iters_per_s"], "cores": base["all_cores"]["cores"]}}
+            res[prec][f"error_vs_fp64_oracle_after_{args.oracle_iters}_iters"] = elementwise_error(Wg, st.w)
+        hc = host_cpu()
+        one = base["one_core"]
+        cpu = {"value": one["iters_per_s"], "unit": "iters/s", "cores": 1, "kind": "oracle",
+               "sample": f"{one['iters']} iterations of the FP64 NumPy oracle at {WORKLOAD} on one BLAS "
+                         f"thread ({one['seconds']:.1f} s)",
+               "host": hc}
+        if "all_cores" in base:
+            al = base["all_cores"]
+            cpu["all_cores"] = {"value": al["iters_per_s"], "cores": al["cores"],
+                                "sample": f"{al['iters']} iterations ({al['seconds']:.1f} s)"}
 
     # headline: the faster precision among those that reach the FP32 error
     head = precs[0]
@@ -345,6 +404,8 @@ def main():
         "config": {"workload": WORKLOAD, "n1": n1, "n2": n2, "n3": n3, "r": r, "sampling": w.p,
                    "mu": w.mu, "rho1": w.rho1, "rho2": w.rho2, "headline_precision": head},
         "hbm_gbps": round(hr["hbm_gbps_algorithmic"], 2),
+        "hbm_frac_whole_iteration": round(hr["hbm_frac_whole_iteration"], 4),
+        "bytes_per_iteration": algorithmic_bytes(n1, n2, n3, r, head == "mixed"),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
                      "kernel": f"{STAGE_KERNELS[dom]} ({dom}, {head})", "kernel_us": round(dom_us, 3),

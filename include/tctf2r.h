@@ -43,7 +43,9 @@ typedef enum {
   TCTF_OK = 0,
   TCTF_E_ARG = -1,        /* NULL pointer or parameter out of range                    */
   TCTF_E_SHAPE = -2,      /* sizes out of the supported range (see tctf_params)         */
-  TCTF_E_NONFINITE = -3,  /* an observed value of G is NaN/Inf, or the iterate became so */
+  TCTF_E_NONFINITE = -3,  /* an observed value of G is NaN/Inf (tctf_create), or a quantity
+                             computed from the iterate (f0, the step-6 differences, the
+                             stationarity measures) is not finite                         */
   TCTF_E_HIP = -4,        /* a HIP runtime call failed (detail in tctf_last_error())    */
   TCTF_E_WORKSPACE = -5,  /* workspace NULL, too small or misaligned (256 B)            */
   TCTF_E_STATE = -6       /* checkpoint blob of the wrong size or for another problem   */
@@ -104,24 +106,34 @@ tctf_status tctf_create(const tctf_params* p, const float* G, const uint8_t* ome
 
 /* Enqueue `iters` iterations (steps 1-4 and 7 of the algorithm box; step 5 keeps r,
  * step 6 is tctf_termination).  Asynchronous and stream-ordered.  Whole blocks of 10
- * iterations are replayed from a HIP graph that the first call needing one captures on a
- * private stream of the context (the results are the same as eager launches). */
+ * iterations are replayed from a HIP graph that the first call with iters >= 1 captures on
+ * a private stream of the context (the results are the same as eager launches); the rest
+ * run as eager launches.  Nothing but the iteration runs unless step 6 is tracked. */
 tctf_status tctf_step(tctf_ctx* c, int32_t iters);
+
+/* Step 6 tracking (algorithm box, step 6).  With on != 0, every later tctf_step call keeps a
+ * copy of X~, Y~ and W~ before its last iteration and evaluates the termination quantities
+ * after it (one device copy of the iterate and one reduction per call), so that
+ * tctf_termination can report them.  Off by default; tctf_run turns it on while it runs. */
+tctf_status tctf_track_termination(tctf_ctx* c, int32_t on);
 
 /* Synchronise and return f0 of eq. (TETP-optim) at the current iterate, accumulated in
  * FP64 (the fit, ridge and K terms from the spatial W-step rows, the H term from the
  * Fourier form eq. (fun-XYW)). */
 tctf_status tctf_objective(tctf_ctx* c, double* f0);
 
-/* Synchronise and return the step-6 quantities of the last iteration:
- * out[0] = ||X~+ - X~||_inf, out[1] = ||Y~+ - Y~||_inf, out[2] = ||W+ - W||_F, and
- * out[3] = 1 if all three are <= eps.  Needs at least one iteration since create. */
+/* Synchronise and return the step-6 quantities of the last iteration of the last tracked
+ * tctf_step call (tctf_track_termination, tctf_run): out[0] = ||X~+ - X~||_inf (largest
+ * entry modulus), out[1] = ||Y~+ - Y~||_inf, out[2] = ||W+ - W||_F, and out[3] = 1 if all
+ * three are <= eps.  TCTF_E_STATE when no tracked iteration ran since create or restore;
+ * TCTF_E_NONFINITE when the iterate is not finite. */
 tctf_status tctf_termination(tctf_ctx* c, double out[4]);
 
 /* Iterate until the step-6 test of the algorithm box holds or max_iters iterations have
- * run: blocks of check_every iterations (tctf_step), each followed by tctf_termination on
- * the block's last iteration.  *iters_run = iterations run by this call; *converged = 1 if
- * the test held (then it held on iteration *iters_run).  Synchronises after every block. */
+ * run: blocks of check_every iterations (tctf_step with step 6 tracked), each followed by
+ * tctf_termination on the block's last iteration.  *iters_run = iterations run by this call;
+ * *converged = 1 if the test held (then it held on iteration *iters_run).  Synchronises
+ * after every block; TCTF_E_NONFINITE if the iterate stops being finite. */
 tctf_status tctf_run(tctf_ctx* c, int32_t max_iters, int32_t check_every, int32_t* iters_run,
                      int32_t* converged);
 
@@ -177,15 +189,52 @@ tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* me
 tctf_status tctf_profile(tctf_ctx* c, uint32_t mask);
 tctf_status tctf_profile_read(tctf_ctx* c, double total_us[7], int64_t launches[7]);
 
+/* ---- Differentiation (reverse mode) of the iteration (section 4.1: eq. (updataXYW1) with
+ * the common step eta, eq. (subquKKT), eq. (bar BA-k) / eq. (barAAk)).  The Grams G_Y and
+ * G_X must have full rank (then their pseudo-inverses are inverses, Lemma SVPMPI).  FP32
+ * contexts only; the adjoint itself runs in FP64 on the context's stream.
+ * Adjoint convention for a real loss L: the adjoint of a complex entry z is
+ * dL/dRe z + i dL/dIm z; a stored frequency b = 0..nb-1 carries the adjoint it has in the
+ * sum over all n3 frequencies (the conjugate frequencies hold the conjugates).  Adjoint
+ * arrays are DEVICE arrays of doubles, complex ones interleaved (re, im):
+ *   xt_bar [nb][r][n1] complex (the layout of X~), yt_bar [nb][r][n2] complex, w_bar
+ *   [n1][n2][n3] real, theta_bar[3] = adjoints of (mu, rho1, rho2).
+ * The adjoint workspace (tctf_adjoint_workspace_bytes, 256-byte aligned) is the caller's. */
+tctf_status tctf_adjoint_workspace_bytes(const tctf_params* p, size_t* bytes);
+
+/* Reverse pass of one iteration.  state_in, state_out: checkpoint blobs (tctf_get_state)
+ * of this context's iterate before and after one iteration (TCTF_E_STATE otherwise).  On
+ * entry xt_bar, yt_bar, w_bar hold the adjoints of X~, Y~ and W after the iteration; on
+ * return those before it (of X~, Y~ and of the W whose transform the iteration read);
+ * the weights' adjoints are ADDED to theta_bar.  Synchronises; TCTF_E_STATE if a Gram is
+ * rank deficient. */
+tctf_status tctf_adjoint_step(tctf_ctx* c, const void* state_in, const void* state_out, double* xt_bar,
+                              double* yt_bar, double* w_bar, double* theta_bar, void* workspace,
+                              size_t ws_bytes);
+
+/* Adjoint of the set-up transforms X~0 = dft(X0), Y~0 = dft(Y0) (eq. (bar BA-k)): the
+ * gradients of L with respect to the real initial factors, x0_bar [n1][r][n3] and y0_bar
+ * [r][n2][n3] (either may be NULL). */
+tctf_status tctf_adjoint_initial(tctf_ctx* c, const double* xt_bar, const double* yt_bar, double* x0_bar,
+                                 double* y0_bar);
+
+/* Gradients of f0 (eq. (TETP-optim)) with respect to the real spatial factors at the
+ * current iterate: through eq. (fun-XYW) and eq. (bar BA-k), d f0 / d X = Re idft(grad_X h)
+ * with grad_X h_k of eq. (hkXYDer), likewise for Y.  x_grad [n1][r][n3], y_grad [r][n2][n3]
+ * doubles.  Uses the adjoint workspace; synchronises. */
+tctf_status tctf_objective_gradient(tctf_ctx* c, double* x_grad, double* y_grad, void* workspace,
+                                    size_t ws_bytes);
+
 /* ---- Batches of independent completions (one level above the per-frequency and per-row
  * separability of one completion, section 3.2).  A batch owns n contexts of possibly
  * different sizes, ranks and parameters, carved from one caller-owned workspace in member
  * order (each member's part 256-byte aligned).  Pointer arguments are HOST arrays of n
  * DEVICE pointers (X0, Y0 and seeds may be NULL, or hold NULL entries, as in tctf_create).
- * tctf_batch_step enqueues `iters` iterations of every member: blocks of 10 iterations of
- * all members run as ONE graph launch in which each member's chain is an independent
- * branch (members are spread over 16 branches), then each member's remaining iterations
- * run as tctf_step would.  Results are the same as running every member alone.
+ * tctf_batch_step enqueues `iters` iterations of every member, all inside graph launches:
+ * blocks of 10 iterations of all members run as ONE graph launch in which each member's
+ * chain is an independent branch (members are spread over 16 branches), and the remaining
+ * iterations as launches of a one-iteration graph of the same form.  Results are the same
+ * as running every member alone.  Step 6 is not evaluated inside a batch step.
  * tctf_batch_member gives member k's context for the per-completion calls (objective,
  * termination, results, checkpoints); it stays owned by the batch. */
 typedef struct tctf_batch tctf_batch;

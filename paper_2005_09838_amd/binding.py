@@ -63,6 +63,11 @@ def library() -> ctypes.CDLL:
         "tctf_time_stage": (I32, [P, I32, I32, ctypes.POINTER(D)]),
         "tctf_profile": (I32, [P, ctypes.c_uint32]),
         "tctf_run": (I32, [P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "tctf_track_termination": (I32, [P, I32]),
+        "tctf_adjoint_workspace_bytes": (I32, [PP, ctypes.POINTER(S)]),
+        "tctf_adjoint_step": (I32, [P, P, P, P, P, P, P, P, S]),
+        "tctf_adjoint_initial": (I32, [P, P, P, P, P]),
+        "tctf_objective_gradient": (I32, [P, P, P, P, S]),
         "tctf_batch_workspace_bytes": (I32, [I32, PP, ctypes.POINTER(S)]),
         "tctf_batch_create": (I32, [I32, PP, P, P, P, P, P, P, S, P, ctypes.POINTER(P)]),
         "tctf_batch_step": (I32, [P, I32]),
@@ -120,6 +125,10 @@ def tctf_step(ctx, iters: int):
     _check(library().tctf_step(ctx, iters), "tctf_step")
 
 
+def tctf_track_termination(ctx, on: bool):
+    _check(library().tctf_track_termination(ctx, 1 if on else 0), "tctf_track_termination")
+
+
 def tctf_objective(ctx) -> float:
     v = ctypes.c_double()
     _check(library().tctf_objective(ctx, ctypes.byref(v)), "tctf_objective")
@@ -173,6 +182,27 @@ def tctf_complete(p: tctf_params, G, omega, X0, Y0, seed: int, iters: int, works
                                    _ptr(workspace), ws_bytes, stream, _ptr(W_out), ctypes.byref(f0)),
            "tctf_complete")
     return f0.value
+
+
+def tctf_adjoint_workspace_bytes(p: tctf_params) -> int:
+    n = ctypes.c_size_t(0)
+    _check(library().tctf_adjoint_workspace_bytes(ctypes.byref(p), ctypes.byref(n)), "tctf_adjoint_workspace_bytes")
+    return n.value
+
+
+def tctf_adjoint_step(ctx, state_in, state_out, xt_bar, yt_bar, w_bar, theta_bar, workspace, ws_bytes: int):
+    _check(library().tctf_adjoint_step(ctx, _ptr(state_in), _ptr(state_out), _ptr(xt_bar), _ptr(yt_bar), _ptr(w_bar),
+                                       _ptr(theta_bar), _ptr(workspace), ws_bytes), "tctf_adjoint_step")
+
+
+def tctf_adjoint_initial(ctx, xt_bar, yt_bar, x0_bar, y0_bar):
+    _check(library().tctf_adjoint_initial(ctx, _ptr(xt_bar), _ptr(yt_bar), _ptr(x0_bar), _ptr(y0_bar)),
+           "tctf_adjoint_initial")
+
+
+def tctf_objective_gradient(ctx, x_grad, y_grad, workspace, ws_bytes: int):
+    _check(library().tctf_objective_gradient(ctx, _ptr(x_grad), _ptr(y_grad), _ptr(workspace), ws_bytes),
+           "tctf_objective_gradient")
 
 
 def tctf_time_stage(ctx, stage: int, reps: int) -> float:
@@ -292,6 +322,11 @@ class Completion:
                "tctf_run")
         return n.value, bool(conv.value)
 
+    def track_termination(self, on=True):
+        """Evaluate step 6 after every later step() call (needed by termination())."""
+        tctf_track_termination(self.ctx, on)
+        return self
+
     def objective(self):
         return tctf_objective(self.ctx)
 
@@ -320,6 +355,24 @@ class Completion:
             out["Y"] = torch.empty((self.r, n2, n3), dtype=torch.float32, device=dev)
         tctf_get_result(self.ctx, out.get("W"), out.get("Z"), out.get("X"), out.get("Y"))
         return out
+
+    def adjoint_workspace(self):
+        """(pointer, bytes) of this completion's adjoint workspace (a torch tensor, made once)."""
+        if getattr(self, "_adj_ws", None) is None:
+            n = tctf_adjoint_workspace_bytes(self.params)
+            buf = self.torch.empty(n + 256, dtype=self.torch.uint8, device=self.G.device)
+            self._adj_ws = (buf, (buf.data_ptr() + 255) & ~255, n)
+        return self._adj_ws[1], self._adj_ws[2]
+
+    def objective_gradient(self):
+        """(d f0 / d X, d f0 / d Y) at the current iterate: float64 tensors [n1][r][n3], [r][n2][n3]."""
+        torch = self.torch
+        n1, n2, n3 = self.shape
+        gx = torch.empty((n1, self.r, n3), dtype=torch.float64, device=self.G.device)
+        gy = torch.empty((self.r, n2, n3), dtype=torch.float64, device=self.G.device)
+        ws, nbytes = self.adjoint_workspace()
+        tctf_objective_gradient(self.ctx, gx, gy, ws, nbytes)
+        return gx, gy
 
     def get_state(self):
         n = tctf_state_bytes(self.ctx)

@@ -105,7 +105,8 @@ static Layout make_layout(const tctf_params& p) {
   L.xt_prev = take(nb * r * n1 * 8);
   L.yt_prev = take(nb * r * n2 * 8);
   L.wt_prev = take(n1 * nb * n2 * welem);
-  L.stat_work = take((nb * 8 + 256) * 8);
+  const size_t sw = nb * 8 > tctf::termination_work_doubles() ? nb * 8 : tctf::termination_work_doubles();
+  L.stat_work = take((sw + 256) * 8);
   L.kkt = take(n1 * 3 * 8);
   L.total = o;
   L.state_bytes = sizeof(StateHeader) + nb * r * n1 * 8 + nb * r * n2 * 8 + n1 * nb * n2 * welem +
@@ -121,6 +122,7 @@ struct tctf_ctx {
   int device;
   int64_t iters;
   bool term_valid;
+  bool track = false;   // step 6 evaluated after every tctf_step call (tctf_track_termination)
   // stage timing of tctf_step (tctf_profile): one event pair per profiled launch
   uint32_t prof_mask = 0;
   std::vector<hipEvent_t> prof_ev;
@@ -267,30 +269,26 @@ static tctf_status enqueue_iteration(tctf_ctx* c) {
   return check_launch();
 }
 
-tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* omega, const float* X0,
-                        const float* Y0, uint64_t seed, void* workspace, size_t ws_bytes, void* hip_stream,
-                        tctf_ctx** out) {
+// Set up a context in caller-provided storage (no host or device allocation): validate,
+// carve the workspace, pack G and Omega, transform the initial factors, form W0, W~0 and
+// the first pseudo-inverses.  On failure the context holds nothing that needs releasing.
+static tctf_status ctx_init(tctf_ctx* c, const tctf_params* prm, const float* G, const uint8_t* omega,
+                            const float* X0, const float* Y0, uint64_t seed, void* workspace, size_t ws_bytes,
+                            void* hip_stream) {
   tctf_status s = validate(prm);
   if (s != TCTF_OK) return s;
-  if (!out) return fail(TCTF_E_ARG, "out is NULL");
-  *out = nullptr;
   if (!G || !omega) return fail(TCTF_E_ARG, "G and omega must be device pointers");
   const Layout L = make_layout(*prm);
   if (!workspace) return fail(TCTF_E_WORKSPACE, "workspace is NULL");
   if (((uintptr_t)workspace & 255u) != 0) return fail(TCTF_E_WORKSPACE, "workspace must be 256-byte aligned");
   if (ws_bytes < L.total) return fail(TCTF_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
-  tctf_ctx* c = new (std::nothrow) tctf_ctx();
-  if (!c) return fail(TCTF_E_ARG, "out of host memory");
   c->prm = *prm;
   c->lay = L;
   c->ws = (unsigned char*)workspace;
   c->iters = 0;
   c->term_valid = false;
   hipError_t e = hipGetDevice(&c->device);
-  if (e != hipSuccess) {
-    delete c;   // nothing created yet
-    return fail(TCTF_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
-  }
+  if (e != hipSuccess) return fail(TCTF_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
   fill_plan(c, (hipStream_t)hip_stream);
   const Plan& p = c->plan;
   tctf::slice_set_attr(p.n3, tctf::slice_launch_lds_bytes(p.n2, p.n3, p.r));
@@ -316,24 +314,52 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   tctf::launch_ystep(p, 1);
   tctf::launch_pinvy(p, p.stream);
   s = check_launch();
-  if (s != TCTF_OK) { tctf_destroy(c); return s; }
+  if (s != TCTF_OK) return s;
   int flag = 0;
   e = hipMemcpyAsync(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost, p.stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
-  if (e != hipSuccess) {
-    tctf_destroy(c);
-    return fail(TCTF_E_HIP, "create: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return fail(TCTF_E_HIP, "create: %s", hipGetErrorString(e));
+  if (flag) return fail(TCTF_E_NONFINITE, "an observed value of G is NaN or Inf");
+  return TCTF_OK;
+}
+
+// Release what a context created after ctx_init (events, graph, capture stream).
+static void ctx_release(tctf_ctx* c) {
+  for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
+  c->prof_ev.clear();
+  if (c->graph_exec) {
+    (void)hipStreamSynchronize(c->plan.stream);   // no replay of the graph may be in flight
+    hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
   }
-  if (flag) {
-    tctf_destroy(c);
-    return fail(TCTF_E_NONFINITE, "an observed value of G is NaN or Inf");
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph = nullptr;
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  c->cap_stream = nullptr;
+}
+
+tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* omega, const float* X0,
+                        const float* Y0, uint64_t seed, void* workspace, size_t ws_bytes, void* hip_stream,
+                        tctf_ctx** out) {
+  if (!out) return fail(TCTF_E_ARG, "out is NULL");
+  *out = nullptr;
+  tctf_status s = validate(prm);
+  if (s != TCTF_OK) return s;
+  tctf_ctx* c = new (std::nothrow) tctf_ctx();
+  if (!c) return fail(TCTF_E_ARG, "out of host memory");
+  s = ctx_init(c, prm, G, omega, X0, Y0, seed, workspace, ws_bytes, hip_stream);
+  if (s != TCTF_OK) {
+    ctx_release(c);
+    delete c;
+    return s;
   }
   *out = c;
   return TCTF_OK;
 }
 
-// Capture GRAPH_ITERS iterations into a graph (once per context).  The kernels take the
-// same buffers every iteration, so one graph serves every later call.
+// Capture GRAPH_ITERS iterations into a graph (once per context, by the first tctf_step call
+// whatever its length, so that a warm-up pays for it).  The kernels take the same buffers
+// every iteration, so one graph serves every later call.  A failed capture leaves no graph.
 static tctf_status ensure_graph(tctf_ctx* c) {
   if (c->graph_exec) return TCTF_OK;
   if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -344,38 +370,46 @@ static tctf_status ensure_graph(tctf_ctx* c) {
   if (e == hipSuccess) {
     for (int k = 0; k < GRAPH_ITERS && s == TCTF_OK; ++k) s = enqueue_iteration(c);
     hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(c->cap_stream, &g);
-    if (e == hipSuccess) {
-      c->graph = g;
-      e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    if (s == TCTF_OK && e2 == hipSuccess) {
+      hipGraphExec_t x = nullptr;
+      e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      if (e == hipSuccess) {
+        c->graph = g;
+        c->graph_exec = x;
+      } else {
+        hipGraphDestroy(g);
+      }
+    } else {
+      if (g) hipGraphDestroy(g);
+      if (e2 != hipSuccess) e = e2;
     }
   }
   c->plan.stream = user;
   if (s != TCTF_OK) return s;
-  if (e != hipSuccess) {
-    c->graph_exec = nullptr;
-    return fail(TCTF_E_HIP, "graph capture of the iteration: %s", hipGetErrorString(e));
-  }
+  if (e != hipSuccess) return fail(TCTF_E_HIP, "graph capture of the iteration: %s", hipGetErrorString(e));
   return TCTF_OK;
 }
 
 tctf_status tctf_step(tctf_ctx* c, int32_t iters) {
   if (!c) return fail(TCTF_E_ARG, "context is NULL");
   if (iters < 0) return fail(TCTF_E_ARG, "iters must be >= 0");
+  if (iters == 0) return TCTF_OK;
   const Plan& p = c->plan;
-  int32_t it = 0;
   // whole blocks of GRAPH_ITERS iterations as graph replays (not while stages are being
-  // timed); the last iteration always runs eagerly after the termination snapshot
-  if (c->prof_mask == 0 && iters - 1 >= GRAPH_ITERS) {
+  // timed); when step 6 is tracked the last iteration runs eagerly after the snapshot
+  const int32_t body = c->track ? iters - 1 : iters;
+  int32_t it = 0;
+  if (c->prof_mask == 0) {
     tctf_status s = ensure_graph(c);
     if (s != TCTF_OK) return s;
-    for (; iters - 1 - it >= GRAPH_ITERS; it += GRAPH_ITERS) {
+    for (; body - it >= GRAPH_ITERS; it += GRAPH_ITERS) {
       HIP_TRY(hipGraphLaunch(c->graph_exec, p.stream));
       c->iters += GRAPH_ITERS;
     }
   }
   for (; it < iters; ++it) {
-    if (it == iters - 1) {
+    if (c->track && it == iters - 1) {
       const size_t welem = tctf::wt_elem_bytes(p);
       HIP_TRY(hipMemcpyAsync(p.xt_prev, p.xt, (size_t)p.nb * p.r * p.n1 * 8, hipMemcpyDeviceToDevice, p.stream));
       HIP_TRY(hipMemcpyAsync(p.yt_prev, p.yt, (size_t)p.nb * p.r * p.n2 * 8, hipMemcpyDeviceToDevice, p.stream));
@@ -385,11 +419,17 @@ tctf_status tctf_step(tctf_ctx* c, int32_t iters) {
     if (s != TCTF_OK) return s;
     c->iters++;
   }
-  if (iters > 0) {
+  if (c->track) {
     tctf::launch_termination(p);
     c->term_valid = true;
   }
   return check_launch();
+}
+
+tctf_status tctf_track_termination(tctf_ctx* c, int32_t on) {
+  if (!c) return fail(TCTF_E_ARG, "context is NULL");
+  c->track = on != 0;
+  return TCTF_OK;
 }
 
 static tctf_status read_scalars(tctf_ctx* c, int first, int count, double* dst) {
@@ -412,9 +452,12 @@ tctf_status tctf_objective(tctf_ctx* c, double* f0) {
 
 tctf_status tctf_termination(tctf_ctx* c, double out[4]) {
   if (!c || !out) return fail(TCTF_E_ARG, "NULL argument");
-  if (!c->term_valid) return fail(TCTF_E_STATE, "no iteration has run since create or restore");
+  if (!c->term_valid)
+    return fail(TCTF_E_STATE, "no tracked iteration since create or restore (tctf_track_termination or tctf_run)");
   tctf_status s = read_scalars(c, 4, 3, out);
   if (s != TCTF_OK) return s;
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1]) || !std::isfinite(out[2]))
+    return fail(TCTF_E_NONFINITE, "the iterate is not finite (step-6 differences %g %g %g)", out[0], out[1], out[2]);
   const double eps = c->prm.eps;
   out[3] = (out[0] <= eps && out[1] <= eps && out[2] <= eps) ? 1.0 : 0.0;
   return TCTF_OK;
@@ -426,20 +469,24 @@ tctf_status tctf_run(tctf_ctx* c, int32_t max_iters, int32_t check_every, int32_
   if (max_iters < 0 || check_every < 1) return fail(TCTF_E_ARG, "max_iters must be >= 0 and check_every >= 1");
   *iters_run = 0;
   *converged = 0;
+  const bool was_tracking = c->track;
+  c->track = true;
+  tctf_status s = TCTF_OK;
   while (*iters_run < max_iters) {
     const int32_t k = check_every < max_iters - *iters_run ? check_every : max_iters - *iters_run;
-    tctf_status s = tctf_step(c, k);
-    if (s != TCTF_OK) return s;
+    s = tctf_step(c, k);
+    if (s != TCTF_OK) break;
     *iters_run += k;
     double t[4];
     s = tctf_termination(c, t);
-    if (s != TCTF_OK) return s;
+    if (s != TCTF_OK) break;
     if (t[3] != 0.0) {
       *converged = 1;
       break;
     }
   }
-  return TCTF_OK;
+  c->track = was_tracking;
+  return s;
 }
 
 tctf_status tctf_stationarity(tctf_ctx* c, double out[3]) {
@@ -447,7 +494,11 @@ tctf_status tctf_stationarity(tctf_ctx* c, double out[3]) {
   tctf::launch_stationarity(c->plan, c->iters == 0 ? 1 : 0);
   tctf_status s = check_launch();
   if (s != TCTF_OK) return s;
-  return read_scalars(c, 8, 3, out);
+  s = read_scalars(c, 8, 3, out);
+  if (s != TCTF_OK) return s;
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1]) || !std::isfinite(out[2]))
+    return fail(TCTF_E_NONFINITE, "the iterate is not finite (stationarity %g %g %g)", out[0], out[1], out[2]);
+  return TCTF_OK;
 }
 
 tctf_status tctf_get_result(tctf_ctx* c, float* W, float* Z, float* X, float* Y) {
@@ -544,14 +595,7 @@ tctf_status tctf_iterations(tctf_ctx* c, int64_t* iters) {
 
 void tctf_destroy(tctf_ctx* c) {
   if (!c) return;
-  for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
-  if (c->graph_exec) {
-    (void)hipStreamSynchronize(c->plan.stream);   // no replay of the graph may be in flight
-    hipGraphExecDestroy(c->graph_exec);
-  }
-  if (c->graph) hipGraphDestroy(c->graph);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-
+  ctx_release(c);
   delete c;
 }
 
@@ -626,6 +670,103 @@ tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* me
   return check_launch();
 }
 
+// ---- differentiation
+static tctf_status adjoint_plan(const tctf_params* prm, Plan* q) {
+  tctf_status s = validate(prm);
+  if (s != TCTF_OK) return s;
+  if (prm->precision != TCTF_FP32) return fail(TCTF_E_ARG, "the adjoint supports FP32 contexts only");
+  std::memset((void*)q, 0, sizeof(*q));
+  q->n1 = prm->n1;
+  q->n2 = prm->n2;
+  q->n3 = prm->n3;
+  q->r = prm->r;
+  q->nb = prm->n3 / 2 + 1;
+  return TCTF_OK;
+}
+
+tctf_status tctf_adjoint_workspace_bytes(const tctf_params* p, size_t* bytes) {
+  if (!bytes) return fail(TCTF_E_ARG, "bytes is NULL");
+  Plan q;
+  tctf_status s = adjoint_plan(p, &q);
+  if (s != TCTF_OK) return s;
+  *bytes = tctf::adjoint_work_bytes(q);
+  return TCTF_OK;
+}
+
+static tctf_status adjoint_workspace(tctf_ctx* c, void* ws, size_t ws_bytes, tctf::AdjWork* w) {
+  if (c->prm.precision != TCTF_FP32) return fail(TCTF_E_ARG, "the adjoint supports FP32 contexts only");
+  if (!ws) return fail(TCTF_E_WORKSPACE, "adjoint workspace is NULL");
+  if (((uintptr_t)ws & 255u) != 0) return fail(TCTF_E_WORKSPACE, "adjoint workspace must be 256-byte aligned");
+  const size_t need = tctf::adjoint_work_bytes(c->plan);
+  if (ws_bytes < need) return fail(TCTF_E_WORKSPACE, "adjoint workspace has %zu bytes, %zu needed", ws_bytes, need);
+  tctf::adjoint_carve(c->plan, ws, w);
+  tctf::adjoint_set_attr(c->plan.r);
+  return TCTF_OK;
+}
+
+// Header of a checkpoint blob in device memory, checked against the context.
+static tctf_status blob_header(tctf_ctx* c, const void* blob, StateHeader* h) {
+  HIP_TRY(hipMemcpyAsync(h, blob, sizeof(*h), hipMemcpyDeviceToHost, c->plan.stream));
+  HIP_TRY(hipStreamSynchronize(c->plan.stream));
+  if (h->magic != kStateMagic || h->n1 != c->plan.n1 || h->n2 != c->plan.n2 || h->n3 != c->plan.n3 ||
+      h->r != c->plan.r || h->precision != c->prm.precision)
+    return fail(TCTF_E_STATE, "state blob belongs to another problem");
+  return TCTF_OK;
+}
+
+static tctf::AdjState blob_state(tctf_ctx* c, const void* blob) {
+  const Plan& p = c->plan;
+  const unsigned char* b = (const unsigned char*)blob + sizeof(StateHeader);
+  tctf::AdjState st;
+  st.xt = (const float2*)b;
+  st.yt = (const float2*)(b + (size_t)p.nb * p.r * p.n1 * 8);
+  st.wt = (const float2*)(b + (size_t)p.nb * p.r * p.n1 * 8 + (size_t)p.nb * p.r * p.n2 * 8);
+  return st;
+}
+
+tctf_status tctf_adjoint_step(tctf_ctx* c, const void* state_in, const void* state_out, double* xt_bar,
+                              double* yt_bar, double* w_bar, double* theta_bar, void* workspace, size_t ws_bytes) {
+  if (!c || !state_in || !state_out || !xt_bar || !yt_bar || !w_bar || !theta_bar)
+    return fail(TCTF_E_ARG, "NULL argument");
+  tctf::AdjWork w;
+  tctf_status s = adjoint_workspace(c, workspace, ws_bytes, &w);
+  if (s != TCTF_OK) return s;
+  StateHeader hi, ho;
+  if ((s = blob_header(c, state_in, &hi)) != TCTF_OK) return s;
+  if ((s = blob_header(c, state_out, &ho)) != TCTF_OK) return s;
+  if (ho.iters != hi.iters + 1)
+    return fail(TCTF_E_STATE, "state_out (iteration %lld) must follow state_in (iteration %lld) by one iteration",
+                (long long)ho.iters, (long long)hi.iters);
+  tctf::launch_adjoint_step(c->plan, w, blob_state(c, state_in), blob_state(c, state_out), (double2*)xt_bar,
+                            (double2*)yt_bar, w_bar, theta_bar);
+  s = check_launch();
+  if (s != TCTF_OK) return s;
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, c->plan.stream));
+  HIP_TRY(hipStreamSynchronize(c->plan.stream));
+  if (flag) return fail(TCTF_E_STATE, "a Gram of this iteration is rank deficient; the adjoint needs full rank");
+  return TCTF_OK;
+}
+
+tctf_status tctf_adjoint_initial(tctf_ctx* c, const double* xt_bar, const double* yt_bar, double* x0_bar,
+                                 double* y0_bar) {
+  if (!c || !xt_bar || !yt_bar) return fail(TCTF_E_ARG, "NULL argument");
+  tctf::launch_adjoint_initial(c->plan, (const double2*)xt_bar, (const double2*)yt_bar, x0_bar, y0_bar);
+  return check_launch();
+}
+
+tctf_status tctf_objective_gradient(tctf_ctx* c, double* x_grad, double* y_grad, void* workspace, size_t ws_bytes) {
+  if (!c || !x_grad || !y_grad) return fail(TCTF_E_ARG, "NULL argument");
+  tctf::AdjWork w;
+  tctf_status s = adjoint_workspace(c, workspace, ws_bytes, &w);
+  if (s != TCTF_OK) return s;
+  tctf::launch_objective_gradient(c->plan, w, x_grad, y_grad);
+  s = check_launch();
+  if (s != TCTF_OK) return s;
+  HIP_TRY(hipStreamSynchronize(c->plan.stream));
+  return TCTF_OK;
+}
+
 const char* tctf_status_string(tctf_status s) {
   switch (s) {
     case TCTF_OK: return "ok";
@@ -654,8 +795,8 @@ struct tctf_batch {
   hipStream_t origin = nullptr;       // capture origin
   hipEvent_t fork_ev = nullptr;
   std::vector<hipEvent_t> done_ev;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};          // [0]: GRAPH_ITERS iterations, [1]: one
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
   hipStream_t stream = nullptr;       // the caller's stream
 };
 
@@ -678,11 +819,11 @@ tctf_status tctf_batch_workspace_bytes(int32_t n, const tctf_params* p, size_t* 
 
 void tctf_batch_destroy(tctf_batch* b) {
   if (!b) return;
-  if (b->graph_exec) {
-    (void)hipStreamSynchronize(b->stream);
-    hipGraphExecDestroy(b->graph_exec);
+  if (b->graph_exec[0] || b->graph_exec[1]) (void)hipStreamSynchronize(b->stream);
+  for (int k = 0; k < 2; ++k) {
+    if (b->graph_exec[k]) hipGraphExecDestroy(b->graph_exec[k]);
+    if (b->graph[k]) hipGraphDestroy(b->graph[k]);
   }
-  if (b->graph) hipGraphDestroy(b->graph);
   for (hipEvent_t e : b->done_ev) hipEventDestroy(e);
   if (b->fork_ev) hipEventDestroy(b->fork_ev);
   for (hipStream_t s : b->streams) hipStreamDestroy(s);
@@ -725,8 +866,11 @@ tctf_status tctf_batch_create(int32_t n, const tctf_params* p, const float* cons
   return TCTF_OK;
 }
 
-static tctf_status batch_graph(tctf_batch* b) {
-  if (b->graph_exec) return TCTF_OK;
+// Graph k of the batch: GRAPH_ITERS iterations (k = 0) or one (k = 1) of every member, each
+// member's chain on one of the branches.  A failed capture leaves no graph.
+static tctf_status batch_graph(tctf_batch* b, int k) {
+  if (b->graph_exec[k]) return TCTF_OK;
+  const int iters = k == 0 ? GRAPH_ITERS : 1;
   const int nbr = (int)b->members.size() < BATCH_BRANCHES ? (int)b->members.size() : BATCH_BRANCHES;
   if (!b->origin) HIP_TRY(hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking));
   if (!b->fork_ev) HIP_TRY(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
@@ -743,9 +887,9 @@ static tctf_status batch_graph(tctf_batch* b) {
   tctf_status s = TCTF_OK;
   for (int q = 0; q < nbr && e == hipSuccess && s == TCTF_OK; ++q) {
     e = hipStreamWaitEvent(b->streams[q], b->fork_ev, 0);
-    for (int it = 0; it < GRAPH_ITERS && e == hipSuccess && s == TCTF_OK; ++it) {
-      for (size_t k = q; k < b->members.size() && s == TCTF_OK; k += nbr) {
-        tctf_ctx* c = b->members[k];
+    for (int it = 0; it < iters && e == hipSuccess && s == TCTF_OK; ++it) {
+      for (size_t m = q; m < b->members.size() && s == TCTF_OK; m += nbr) {
+        tctf_ctx* c = b->members[m];
         const hipStream_t user = c->plan.stream;
         c->plan.stream = b->streams[q];
         s = enqueue_iteration(c);
@@ -757,38 +901,38 @@ static tctf_status batch_graph(tctf_batch* b) {
   }
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(b->origin, &g);
-  if (s != TCTF_OK) {
+  if (s != TCTF_OK || e != hipSuccess || e2 != hipSuccess) {
     if (g) hipGraphDestroy(g);
-    return s;
+    if (s != TCTF_OK) return s;
+    return fail(TCTF_E_HIP, "graph capture of the batch: %s", hipGetErrorString(e != hipSuccess ? e : e2));
   }
-  if (e == hipSuccess) e = e2;
-  if (e == hipSuccess) {
-    b->graph = g;
-    e = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
-  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
-    b->graph_exec = nullptr;
-    return fail(TCTF_E_HIP, "graph capture of the batch: %s", hipGetErrorString(e));
+    hipGraphDestroy(g);
+    return fail(TCTF_E_HIP, "graph instantiation of the batch: %s", hipGetErrorString(e));
   }
+  b->graph[k] = g;
+  b->graph_exec[k] = x;
   return TCTF_OK;
 }
 
 tctf_status tctf_batch_step(tctf_batch* b, int32_t iters) {
   if (!b) return fail(TCTF_E_ARG, "batch is NULL");
   if (iters < 0) return fail(TCTF_E_ARG, "iters must be >= 0");
-  int32_t it = 0;
-  if (iters - 1 >= GRAPH_ITERS) {
-    tctf_status s = batch_graph(b);
+  if (iters == 0) return TCTF_OK;
+  // every iteration of every member runs inside a graph launch: blocks of GRAPH_ITERS, then
+  // the one-iteration graph for the remainder (both captured by the first call)
+  for (int k = 0; k < 2; ++k) {
+    tctf_status s = batch_graph(b, k);
     if (s != TCTF_OK) return s;
-    for (; iters - 1 - it >= GRAPH_ITERS; it += GRAPH_ITERS) {
-      HIP_TRY(hipGraphLaunch(b->graph_exec, b->stream));
-      for (tctf_ctx* c : b->members) c->iters += GRAPH_ITERS;
-    }
   }
-  // the remainder (always including the last iteration and its termination snapshot)
+  int32_t it = 0;
+  for (; iters - it >= GRAPH_ITERS; it += GRAPH_ITERS) HIP_TRY(hipGraphLaunch(b->graph_exec[0], b->stream));
+  for (; it < iters; ++it) HIP_TRY(hipGraphLaunch(b->graph_exec[1], b->stream));
   for (tctf_ctx* c : b->members) {
-    tctf_status s = tctf_step(c, iters - it);
-    if (s != TCTF_OK) return s;
+    c->iters += iters;
+    c->term_valid = false;   // step 6 is not evaluated inside batch graphs
   }
   return TCTF_OK;
 }

@@ -78,6 +78,39 @@ void pinvy_set_attr(int r);
 void zgemm_set_attr(int r);
 void launch_objective(const Plan& p);
 void launch_termination(const Plan& p);
+size_t termination_work_doubles();   // partials of the step-6 reduction held in stat_work
 void launch_stationarity(const Plan& p, int w_from_g);
+
+// differentiation (reverse mode) of one iteration, FP64 (kernels_adjoint.hip)
+// Complex matrix batch view: element (b, i, j) at b bs + i rs + j cs of float2 (f32 = 1) or
+// double2 storage, conjugated on load when conj = 1.
+struct CView {
+  const void* p;
+  long bs, rs, cs;
+  int f32, conj;
+};
+struct AdjState {        // forward values of one iterate (inside a checkpoint blob)
+  const float2* xt;      // X~ [nb][r][n1]
+  const float2* yt;      // Y~ [nb][r][n2]
+  const float2* wt;      // W~ [n1][nb][n2]
+};
+struct AdjWork {         // adjoint scratch carved from the caller's adjoint workspace
+  double *w1s, *cbuf, *zbar;
+  double2 *ztb, *wtb;
+  double2 *x1b, *hx1, *a, *pp, *q, *pb, *qb, *ab, *dt;
+  double2 *y1b, *bm, *bb, *rb;
+  double2 *gy, *gyi, *gx, *gxi, *gyib, *gxib, *gyb, *gxb, *S, *T, *tmp;
+  double* htab;
+  double* part;
+  int* flag;
+};
+size_t adjoint_work_bytes(const Plan& p);
+void adjoint_carve(const Plan& p, void* ws, AdjWork* w);
+void adjoint_set_attr(int r);
+void launch_adjoint_step(const Plan& p, const AdjWork& w, const AdjState& in, const AdjState& out, double2* xt_bar,
+                         double2* yt_bar, double* w_bar, double* theta);
+void launch_adjoint_initial(const Plan& p, const double2* xt_bar, const double2* yt_bar, double* x0_bar,
+                            double* y0_bar);
+void launch_objective_gradient(const Plan& p, const AdjWork& w, double* x_grad, double* y_grad);
 
 }  // namespace tctf

@@ -215,7 +215,12 @@ void launch_objective(const Plan& p) {
 // Step 6 quantities between the snapshot and the current iterate:
 // max |dX~|, max |dY~| (the maxima over stored frequencies equal those over all of them)
 // and ||dW||_F from the stored frequencies by Parseval: ||dW||^2 = 1/n3 sum_b c_b ||dW~_b||^2.
-__global__ void k_termination(const float2* __restrict__ x, const float2* __restrict__ xp, long nx,
+// A non-finite difference counts as +inf in the maxima (fmax would drop a NaN) and stays NaN
+// in the sum, so a non-finite iterate shows in the result.  Grid-stride loops over a grid
+// that covers every compute unit; per-block partials, then one block combines them in a
+// fixed order.
+#define TERM_BLOCKS 1024
+__global__ void __launch_bounds__(256) k_termination(const float2* __restrict__ x, const float2* __restrict__ xp, long nx,
                               const float2* __restrict__ y, const float2* __restrict__ yp, long ny,
                               const void* __restrict__ w, const void* __restrict__ wp, int mixed,
                               int n1, int nb, int n2, int n3, double* part) {
@@ -223,8 +228,14 @@ __global__ void k_termination(const float2* __restrict__ x, const float2* __rest
   double mx = 0.0, my = 0.0, sw = 0.0;
   const long stride = (long)gridDim.x * blockDim.x;
   const long t0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  for (long e = t0; e < nx; e += stride) mx = fmax(mx, hypot((double)x[e].x - xp[e].x, (double)x[e].y - xp[e].y));
-  for (long e = t0; e < ny; e += stride) my = fmax(my, hypot((double)y[e].x - yp[e].x, (double)y[e].y - yp[e].y));
+  for (long e = t0; e < nx; e += stride) {
+    const double d = hypot((double)x[e].x - xp[e].x, (double)x[e].y - xp[e].y);
+    mx = (d == d) ? fmax(mx, d) : INFINITY;
+  }
+  for (long e = t0; e < ny; e += stride) {
+    const double d = hypot((double)y[e].x - yp[e].x, (double)y[e].y - yp[e].y);
+    my = (d == d) ? fmax(my, d) : INFINITY;
+  }
   const long nw = (long)n1 * nb * n2;
   for (long e = t0; e < nw; e += stride) {
     const int b = (int)((e / n2) % nb);
@@ -244,26 +255,35 @@ __global__ void k_termination(const float2* __restrict__ x, const float2* __rest
   }
 }
 
-__global__ void k_termination_final(const double* __restrict__ part, int nblk, int n3, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double mx = 0.0, my = 0.0, sw = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      mx = fmax(mx, part[3 * b]);
-      my = fmax(my, part[3 * b + 1]);
-      sw += part[3 * b + 2];
-    }
+__global__ void __launch_bounds__(256) k_termination_final(const double* __restrict__ part, int nblk, int n3, double* out) {
+  __shared__ double red[16];
+  double mx = 0.0, my = 0.0, sw = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    mx = fmax(mx, part[3 * b]);
+    my = fmax(my, part[3 * b + 1]);
+    sw += part[3 * b + 2];
+  }
+  mx = block_max_d(mx, red);
+  my = block_max_d(my, red);
+  sw = block_sum_d(sw, red);
+  if (threadIdx.x == 0) {
     out[0] = mx;
     out[1] = my;
     out[2] = sqrt(sw / n3);
   }
 }
 
+size_t termination_work_doubles() { return 3 * TERM_BLOCKS; }
+
 void launch_termination(const Plan& p) {
-  const int nblk = 64;
+  const long nw = (long)p.n1 * p.nb * p.n2;
+  int nblk = (int)((nw + 1023) / 1024);
+  if (nblk > TERM_BLOCKS) nblk = TERM_BLOCKS;
+  if (nblk < 1) nblk = 1;
   k_termination<<<nblk, 256, 0, p.stream>>>(p.xt, p.xt_prev, (long)p.nb * p.r * p.n1, p.yt, p.yt_prev,
                                             (long)p.nb * p.r * p.n2, p.wt, p.wt_prev, p.mixed, p.n1, p.nb,
                                             p.n2, p.n3, p.stat_work);
-  k_termination_final<<<1, 64, 0, p.stream>>>(p.stat_work, nblk, p.n3, p.scal + 4);
+  k_termination_final<<<1, 256, 0, p.stream>>>(p.stat_work, nblk, p.n3, p.scal + 4);
 }
 
 }  // namespace tctf

@@ -86,3 +86,12 @@ def test_create_rejects_null_arguments_before_device_work():
     with pytest.raises(B.TctfError) as e:
         B.tctf_create(p, 4096, 4096, None, None, 0, 4096, n - 1, None)
     assert e.value.status == B.TCTF_E_WORKSPACE
+
+
+def test_adjoint_workspace_and_precision_checks():
+    from paper_2005_09838_amd import binding as B
+    n = B.tctf_adjoint_workspace_bytes(B.make_params(144, 288, 28, 8))
+    assert n > 0 and n % 256 == 0
+    with pytest.raises(B.TctfError) as e:
+        B.tctf_adjoint_workspace_bytes(B.make_params(144, 288, 28, 8, precision="mixed"))
+    assert e.value.status == B.TCTF_E_ARG

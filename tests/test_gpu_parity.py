@@ -1,6 +1,11 @@
 """HIP path against the FP64 oracle on the same seeded inputs (needs an MI355X).
 
-Tolerance: relative error (Frobenius) <= 1e-5 for W, Z and f0 in FP32.
+Tolerances (FP32 GPU against the FP64 oracle, same inputs and the same initial factors):
+* relative Frobenius error <= 1e-5 for W, Z and f0;
+* element-wise: max |A_gpu - A_oracle| <= 1e-5 max |A_oracle| for A = W and Z;
+* per OD pair (mode-1 slice i): ||A_gpu(i) - A_oracle(i)|| <= TOL_ROW ||A_oracle(i)||, so that
+  an error confined to low-volume OD rows (heavy-tailed scales) or to the ragged tails of
+  the tiles cannot hide under the norm of the large rows.
 """
 import numpy as np
 import pytest
@@ -9,18 +14,36 @@ from tests.gpu_helpers import gpu_run, make_inputs, make_workload, oracle, oracl
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
+TOL_MAX = 1e-5
+TOL_ROW = 5e-5
 
 
-def _compare(g, st, info=None, tol=TOL, label=""):
-    ew = rel(g["W"], st.w)
-    ez = rel(g["Z"], oracle.z_of(st))
-    msg = f"{label} W {ew:.2e} Z {ez:.2e}"
+def elementwise(a, ref):
+    """(relative Frobenius error, max error / max |ref|, worst per-row relative error, its row)."""
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = (a - ref).reshape(ref.shape[0], -1)
+    rn = np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
+    dn = np.linalg.norm(d, axis=1)
+    rowrel = np.where(dn == 0.0, 0.0, dn / np.maximum(rn, 1e-30))
+    emax = float(np.abs(d).max() / max(np.abs(ref).max(), 1e-30)) if ref.size else 0.0
+    worst = int(np.argmax(rowrel)) if ref.size else 0
+    return rel(a, ref), emax, float(rowrel.max()) if ref.size else 0.0, worst
+
+
+def _compare(g, st, info=None, tol=TOL, label="", tol_max=TOL_MAX, tol_row=TOL_ROW):
+    msg = label
+    ok = True
+    for name, ref in (("W", st.w), ("Z", oracle.z_of(st))):
+        fro, emax, erow, irow = elementwise(g[name], ref)
+        msg += f" | {name} fro {fro:.2e} max {emax:.2e} row {erow:.2e} (i={irow})"
+        ok = ok and fro <= tol and emax <= tol_max and erow <= tol_row
     if info is not None and info["f0"]:
         ef = abs(g["f0"][-1] - info["f0"][-1]) / max(abs(info["f0"][-1]), 1e-30)
-        msg += f" f0 {ef:.2e}"
-        assert ef <= tol, msg
+        msg += f" | f0 {ef:.2e}"
+        ok = ok and ef <= tol
     print(msg, flush=True)
-    assert ew <= tol and ez <= tol, msg
+    assert ok, msg
 
 
 def test_smallest_workload_50_iterations():
@@ -111,19 +134,33 @@ def test_eigen_pseudo_inverse_path_and_rank_deficiency():
     _compare(g, st, info, label="rank-deficient start")
 
 
-def test_workload_144x288x28_p40():
+def test_workload_144x288x28_p40_full_run():
+    """144 x 288 x 28, r = 8, 40 % sampled: the whole 200-iteration run against the oracle."""
     w, d = make_workload("od144x288x28_r8_p40")
+    g = gpu_run(d, w.r, w.iters)
+    st, info = oracle_run(d, w.r, w.iters)
+    info["f0"] = [oracle.objective(info["problem"], st)]
+    _compare(g, st, info, label=f"od144x288x28_r8_p40 ({w.iters} it)")
+
+
+@pytest.mark.parametrize("p", [10, 20, 60, 80])
+def test_workload_144x288x28_other_rates(p):
+    """The other sampling rates of the same workload, 20 iterations each."""
+    w, d = make_workload(f"od144x288x28_r8_p{p}")
     g = gpu_run(d, w.r, 20)
-    st, info = oracle_run(d, w.r, 20, history=True)
-    _compare(g, st, info, label="od144x288x28_r8_p40 (20 it)")
+    st, info = oracle_run(d, w.r, 20)
+    info["f0"] = [oracle.objective(info["problem"], st)]
+    _compare(g, st, info, label=f"od144x288x28_r8_p{p} (20 it)")
 
 
 def test_precision_workload_full_size_parity():
-    """529 x 96 x 112, r = 16 in the configuration the bench times: 2 iterations vs the oracle."""
+    """529 x 96 x 112, r = 16 in the configuration the bench times (graph replays): 20
+    iterations against the oracle."""
     w, d = make_workload("od529x96x112_r16")
-    g = gpu_run(d, w.r, 2)
-    st, info = oracle_run(d, w.r, 2, history=True)
-    _compare(g, st, info, label="od529x96x112_r16 (2 it)")
+    g = gpu_run(d, w.r, 20)
+    st, info = oracle_run(d, w.r, 20)
+    info["f0"] = [oracle.objective(info["problem"], st)]
+    _compare(g, st, info, label="od529x96x112_r16 (20 it)")
 
 
 def test_factors_in_spatial_domain():
@@ -136,7 +173,7 @@ def test_factors_in_spatial_domain():
 
 def test_stationarity_and_termination_measures():
     d = make_inputs(18, 14, 6, 3, p=0.6, seed=12)
-    g = gpu_run(d, 3, 12)
+    g = gpu_run(d, 3, 12, track=True)
     c = g["ctx"]
     s = c.stationarity()
     t = c.termination()
