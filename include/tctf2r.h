@@ -54,10 +54,14 @@ typedef enum {
 typedef enum {
   TCTF_FP32 = 0,        /* FP32 storage and products; the reduction over n1 of X~^* W~
                            accumulates in FP64; r x r Grams, pseudo-inverses, objective FP64 */
-  TCTF_MIXED_BF16 = 1   /* W~ stored in BF16 (half the bytes of its write and reads); the
-                           slice products take the BF16 W~ and FP32 factors and accumulate
-                           in FP32; factors, G and W stay FP32; r x r Grams, pseudo-inverses
-                           and objective FP64                                                */
+  TCTF_MIXED_BF16 = 1   /* W~ stored in BF16 (half the bytes of its write and reads), rounded
+                           stochastically with counter-based rounding bits keyed by the entry
+                           and the iteration (deterministic and resumable; unlike
+                           round-to-nearest its error does not repeat from one iteration to
+                           the next, so the iteration does not accumulate it); the slice
+                           products take the BF16 W~ and FP32 factors and accumulate in FP32;
+                           factors, G and W stay FP32; r x r Grams, pseudo-inverses and
+                           objective FP64                                                    */
 } tctf_precision;
 
 typedef struct {
@@ -74,9 +78,11 @@ typedef struct {
                            eigenvalue, eigen-decomposition otherwise; 1: always eigen     */
   double eps;           /* threshold of the termination test (step 6), default 1e-6        */
 } tctf_params;
-/* Supported n3: 1..16, 20, 24, 28, 32, 40, 48, 56, 64, 84, 96, 112, 128 (the tube
- * transform is generated for these lengths).  n1 <= 8192, n2 <= 1024, and one slice
- * (n2 x (n3 + 1) floats) must fit the slice kernel's 150 KiB of LDS. */
+/* Sizes: n1 <= 8192, n2 <= 1024, n3 <= 8192.  For n3 in 1..16, 20, 24, 28, 32, 40, 48, 56,
+ * 64, 84, 96, 112, 128 (the lengths the tube transform is generated for) with one slice
+ * (n2 x (n3 + 1) floats) inside 150 KiB, steps 3, 4 and 7 run as one fused kernel per OD
+ * row; any other size runs them as three launches through spatial Z and W buffers (direct
+ * tube transforms; the workspace grows by 12 n1 n2 n3 bytes). */
 
 typedef struct tctf_ctx tctf_ctx;
 

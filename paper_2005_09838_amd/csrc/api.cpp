@@ -50,7 +50,7 @@ struct StateHeader {
 
 struct Layout {
   size_t gp, wt, zt, xt, yt, rhs, bpart, gxm, dmat, gxp, qx, qx_zero, gym, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
-      flag, scal, xt_prev, yt_prev, wt_prev, stat_work, kkt, total;
+      flag, ctr, zsp, wsp, csp, twg, scal, xt_prev, yt_prev, wt_prev, stat_work, kkt, total;
   size_t state_bytes;
 };
 
@@ -101,6 +101,12 @@ static Layout make_layout(const tctf_params& p) {
   L.wtab = take(4 * n2 * 4);
   L.htab = take(3 * n1 * 4);
   L.flag = take(64);
+  L.ctr = take(64);
+  const bool gen = !tctf::slice_fused(p.n2, p.n3);   // the three-launch slice path
+  L.zsp = take(gen ? n1 * n2 * n3 * 4 : 0);
+  L.wsp = take(gen ? n1 * n2 * n3 * 4 : 0);
+  L.csp = take(gen ? n1 * n2 * n3 * 4 : 0);
+  L.twg = take(gen ? n3 * 16 : 0);
   L.scal = take(16 * 8);
   L.xt_prev = take(nb * r * n1 * 8);
   L.yt_prev = take(nb * r * n2 * 8);
@@ -110,7 +116,7 @@ static Layout make_layout(const tctf_params& p) {
   L.kkt = take(n1 * 3 * 8);
   L.total = o;
   L.state_bytes = sizeof(StateHeader) + nb * r * n1 * 8 + nb * r * n2 * 8 + n1 * nb * n2 * welem +
-                  2 * nb * r * r * 16 + nb * 4 + n1 * 3 * 8 + nb * 8;
+                  2 * nb * r * r * 16 + nb * 4 + n1 * 3 * 8 + nb * 8 + 4;
   return L;
 }
 
@@ -144,9 +150,7 @@ static tctf_status validate(const tctf_params* p) {
     return fail(TCTF_E_SHAPE, "rank r=%d must satisfy 1 <= r <= min(n1, n2, %d)", p->r, TCTF_RMAX);
   if (p->n1 > TCTF_N1MAX) return fail(TCTF_E_SHAPE, "n1=%d exceeds %d", p->n1, TCTF_N1MAX);
   if (p->n2 > TCTF_N2MAX) return fail(TCTF_E_SHAPE, "n2=%d exceeds %d", p->n2, TCTF_N2MAX);
-  if (!tctf::slice_supported(p->n3)) return fail(TCTF_E_SHAPE, "n3=%d is not a supported tube length", p->n3);
-  if (tctf::slice_lds_bytes(p->n2, p->n3) > TCTF_SLICE_LDS_MAX)
-    return fail(TCTF_E_SHAPE, "n2 x (n3 + 1) = %d x %d does not fit the slice kernel's LDS", p->n2, p->n3 + 1);
+  if (p->n3 > TCTF_N3MAX) return fail(TCTF_E_SHAPE, "n3=%d exceeds %d", p->n3, TCTF_N3MAX);
   if (!(std::isfinite(p->mu) && p->mu >= 0) || !(std::isfinite(p->rho1) && p->rho1 >= 0) ||
       !(std::isfinite(p->rho2) && p->rho2 >= 0))
     return fail(TCTF_E_ARG, "mu, rho1, rho2 must be finite and >= 0");
@@ -219,6 +223,11 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.wtab = (float*)(w + L.wtab);
   q.htab = (float*)(w + L.htab);
   q.flag = (int*)(w + L.flag);
+  q.ctr = (uint32_t*)(w + L.ctr);
+  q.zsp = (float*)(w + L.zsp);
+  q.wsp = (float*)(w + L.wsp);
+  q.csp = (float*)(w + L.csp);
+  q.twg = (double2*)(w + L.twg);
   q.scal = (double*)(w + L.scal);
   q.xt_prev = (float2*)(w + L.xt_prev);
   q.yt_prev = (float2*)(w + L.yt_prev);
@@ -257,7 +266,7 @@ static tctf_status stage(tctf_ctx* c, int id, F&& launch) {
 static tctf_status enqueue_iteration(tctf_ctx* c) {
   const Plan& p = c->plan;
   tctf_status s = TCTF_OK;
-  if (s == TCTF_OK) s = stage(c, 2, [&] { tctf::launch_agemm(p); });
+  if (s == TCTF_OK) s = stage(c, 2, [&] { tctf::launch_agemm(p, 0, 1); });
   if (s == TCTF_OK) s = stage(c, 3, [&] { tctf::launch_hsolve(p); });
   if (s == TCTF_OK) s = stage(c, 4, [&] { tctf::launch_bgemm(p); });
   if (s == TCTF_OK) s = stage(c, 5, [&] { tctf::launch_ystep(p, 0); });
@@ -297,9 +306,11 @@ static tctf_status ctx_init(tctf_ctx* c, const tctf_params* prm, const float* G,
   tctf::pinvy_set_attr(p.r);
   tctf::zgemm_set_attr(p.r);
   tctf::launch_zero(p, p.flag, 64);
+  tctf::launch_zero(p, p.ctr, 64);
   tctf::launch_zero(p, p.qy_zero, (size_t)p.nb * 4);
   tctf::launch_pack_g(p, G, omega);
   tctf::launch_tables(p);
+  if (!tctf::slice_fused(p.n2, p.n3)) tctf::launch_gen_twiddles(p);
   if (X0) tctf::launch_tube_dft_setup(p, X0, p.xt, p.n1, p.r, (long)p.r * p.n1, 1, p.n1);
   else tctf::launch_zero(p, p.xt, (size_t)p.nb * p.r * p.n1 * 8);
   const float* y0 = Y0;
@@ -532,6 +543,7 @@ static int state_regions(tctf_ctx* c, Region* r) {
   r[n++] = {L.qy_zero, (size_t)p.nb * 4};
   r[n++] = {L.slice_obj, (size_t)p.n1 * 3 * 8};
   r[n++] = {L.bin_obj, (size_t)p.nb * 8};
+  r[n++] = {L.ctr, 4};
   return n;
 }
 

@@ -7,6 +7,7 @@
 #define TCTF_RMAX 32          // largest tubal rank r supported by the r x r kernels
 #define TCTF_N2MAX 1024       // largest n2 (slice kernel: one thread per tube of a slice)
 #define TCTF_N1MAX 8192       // largest n1 (tridiagonal H_rho1 solve held in LDS)
+#define TCTF_N3MAX 8192       // largest tube length n3
 #define TCTF_SLICE_LDS_MAX (150 * 1024)
 
 // Complex numbers: planar pairs in registers, float2 / double2 in memory.
@@ -46,6 +47,28 @@ __host__ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uin
 __host__ __device__ __forceinline__ float bf16_round(float x) { return bf16_to_f32(f32_to_bf16(x)); }
 __host__ __device__ __forceinline__ uint32_t pack_bf16x2(float re, float im) {
   return (uint32_t)f32_to_bf16(re) | ((uint32_t)f32_to_bf16(im) << 16);
+}
+// MurmurHash3's 32-bit finaliser (Appleby): a bijective mixer, used as a counter-based
+// generator of rounding bits.
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+// BF16 by stochastic rounding: the 16 dropped bits are compared with 16 uniform random bits
+// (added, then truncated), so the result rounds up with probability equal to the dropped
+// fraction and its expectation is x.  Unlike round-to-nearest, its error is not the same
+// every time a slowly changing value is rounded.  NaN/Inf as round-to-nearest.
+__host__ __device__ __forceinline__ uint16_t f32_to_bf16_sr(float x, uint32_t rnd16) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return f32_to_bf16(x);
+  return (uint16_t)((u + (rnd16 & 0xffffu)) >> 16);
+}
+__host__ __device__ __forceinline__ uint32_t pack_bf16x2_sr(float re, float im, uint32_t rnd) {
+  return (uint32_t)f32_to_bf16_sr(re, rnd) | ((uint32_t)f32_to_bf16_sr(im, rnd >> 16) << 16);
 }
 __host__ __device__ __forceinline__ float2 unpack_bf16x2(uint32_t v) {
   return make_float2(bf16_to_f32((uint16_t)(v & 0xffffu)), bf16_to_f32((uint16_t)(v >> 16)));

@@ -36,6 +36,13 @@ struct Plan {
   float* wtab;      // [4][n2] reciprocal pivots of the W-step row systems
   float* htab;      // [3][n1] Thomas coefficients of H_rho1
   int* flag;        // non-finite detector
+  uint32_t* ctr;    // iteration counter of the BF16 rounding bits (advanced by each X-step)
+  // the three-launch slice path (tube lengths outside the generated set, or slices larger
+  // than the fused kernel's LDS): spatial Z, W and elimination factors, roots of unity
+  float* zsp;       // [n1][n2][n3]
+  float* wsp;       // [n1][n2][n3]
+  float* csp;       // [n1][n2][n3]
+  double2* twg;     // [n3] (cos, sin)(2 pi m / n3)
   double* scal;     // [16] scalar results (objective, termination, stationarity)
   float2* xt_prev;  // snapshots for the termination test
   float2* yt_prev;
@@ -59,11 +66,14 @@ void launch_zero(const Plan& p, void* dst, size_t bytes);
 // iteration
 enum SliceMode { SLICE_INIT = 0, SLICE_ITER = 1, SLICE_RESULT = 2, SLICE_KKT = 3 };
 bool slice_supported(int n3);
+bool slice_fused(int n2, int n3);          // the fused LDS slice kernel applies
+void launch_gen_twiddles(const Plan& p);
+void launch_slice_generic(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g);
 bool slice_hosts_pinvy(int n2, int n3);   // the iteration's slice launch also forms G_Y^+
 size_t slice_launch_lds_bytes(int n2, int n3, int r);
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g);
 void launch_zgemm(const Plan& p, int with_pinv = 0);   // with_pinv: also G_Y^+ (pinvy_block)
-void launch_agemm(const Plan& p, int raw_a = 0);
+void launch_agemm(const Plan& p, int raw_a = 0, int advance = 0);   // advance: next rounding-bit counter
 void launch_hsolve(const Plan& p);
 void launch_bgemm(const Plan& p);   // also G_X, G_X^+ and I - eta P_X (gramx_block)
 size_t bgemm_lds_bytes(int r, int chunk);

@@ -9,7 +9,8 @@
 // interleaved (re, im) storage itself, with the signs of the complex product placed in the
 // operand that is built on the fly.  X~^* W~ is summed in FP64 over blocks of 16 rows;
 // r x r Grams and the X right-hand side epilogue are FP64.  Mixed mode reads W~ from its
-// BF16 storage and converts to FP32 before the product.
+// BF16 storage (stochastically rounded by the slice kernel) and converts to FP32 before
+// the product.
 #include <type_traits>
 #include "kernels.h"
 #include "pinv.h"
@@ -169,13 +170,16 @@ __global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __r
                                                const float2* __restrict__ xt, const cd* __restrict__ gyp,
                                                const cd* __restrict__ qy, const int* __restrict__ qy_zero,
                                                float2* __restrict__ rhs, int n1, int n2, int r, int nb,
-                                               double eta, double rho1, int raw_a) {
+                                               double eta, double rho1, int raw_a, uint32_t* ctr) {
   __shared__ __align__(16) float2 ysh[RM * AG_COLS];   // [s][j] of the column chunk
   __shared__ __align__(16) float2 ash[AG_ROWS * RM];   // A rows, then the results
   __shared__ __align__(16) cd gs[RM * RM];             // G_Y^+
   const int i0 = blockIdx.x * AG_ROWS, b = blockIdx.y, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
   const int row = i0 + 16 * w + m;
+  // one thread of the launch advances the counter of the rounding bits that this
+  // iteration's slice kernel (a later launch) uses for the BF16 W~
+  if (ctr && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) ctr[0] += 1u;
   constexpr int NNT = RM / 8;          // 16-column tiles of A' (2 RM columns)
   constexpr int YPER = RM * AG_COLS / 256;
   const bool eodd = m & 1;             // this lane's output column 2s + e has e = 1
@@ -326,11 +330,11 @@ __global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __r
   }
 }
 
-void launch_agemm(const Plan& p, int raw_a) {
+void launch_agemm(const Plan& p, int raw_a, int advance) {
   dim3 grid((p.n1 + AG_ROWS - 1) / AG_ROWS, p.nb);
 #define TCTF_AGEMM(RM, MX)                                                                                    \
   k_agemm<RM, MX><<<grid, 256, 0, p.stream>>>(p.wt, p.yt, p.xt, p.gyp, p.qy, p.qy_zero, p.rhs, p.n1, p.n2, p.r, \
-                                              p.nb, p.eta, p.rho1, raw_a)
+                                              p.nb, p.eta, p.rho1, raw_a, advance ? p.ctr : nullptr)
   if (p.mixed) {
     if (p.r <= 8) TCTF_AGEMM(8, true);
     else if (p.r <= 16) TCTF_AGEMM(16, true);

@@ -44,6 +44,7 @@ struct SliceArgs {
   double mu, rho2d;
   int mode, mixed, w_from_g;
   int npinv;     // SLICE_ITER: blocks n1 .. n1 + npinv - 1 form G_Y^+ of frequency blockIdx.x - n1
+  const uint32_t* ctr;   // counter of the BF16 rounding bits (mixed precision)
   PinvyArgs pa;
 };
 
@@ -271,7 +272,10 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
       if constexpr (LDSFFT) {
         if (a.mixed) {
           uint32_t* dst = (uint32_t*)a.wt + base;
-          tube_fwd_lds<N>(row, twm, twn, [&](int b, float re, float im) { dst[(size_t)b * n2] = pack_bf16x2(re, im); });
+          const uint32_t key = fmix32(a.ctr[0] * 0x9e3779b9u + 0x7f4a7c15u);
+          tube_fwd_lds<N>(row, twm, twn, [&](int b, float re, float im) {
+            dst[(size_t)b * n2] = pack_bf16x2_sr(re, im, fmix32((uint32_t)(base + (size_t)b * n2) ^ key));
+          });
         } else {
           float2* dst = (float2*)a.wt + base;
           tube_fwd_lds<N>(row, twm, twn, [&](int b, float re, float im) { dst[(size_t)b * n2] = make_float2(re, im); });
@@ -283,8 +287,10 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
         tube_fwd<N>(w, re, im);
         if (a.mixed) {
           uint32_t* dst = (uint32_t*)a.wt + base;
+          const uint32_t key = fmix32(a.ctr[0] * 0x9e3779b9u + 0x7f4a7c15u);
 #pragma unroll
-          for (int b = 0; b < NB; ++b) dst[(size_t)b * n2] = pack_bf16x2(re[b], im[b]);
+          for (int b = 0; b < NB; ++b)
+            dst[(size_t)b * n2] = pack_bf16x2_sr(re[b], im[b], fmix32((uint32_t)(base + (size_t)b * n2) ^ key));
         } else {
           float2* dst = (float2*)a.wt + base;
 #pragma unroll
@@ -585,7 +591,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
       const size_t base = i * a.nb * n2 + j;
       if (a.mixed) {
         uint32_t* dst = (uint32_t*)a.wt + base;
-        tube_fwd_post_nat<N>(row, twn, t, T, [&](int b, float re, float im) { dst[(size_t)b * n2] = pack_bf16x2(re, im); });
+        const uint32_t key = fmix32(a.ctr[0] * 0x9e3779b9u + 0x7f4a7c15u);
+        tube_fwd_post_nat<N>(row, twn, t, T, [&](int b, float re, float im) {
+          dst[(size_t)b * n2] = pack_bf16x2_sr(re, im, fmix32((uint32_t)(base + (size_t)b * n2) ^ key));
+        });
       } else {
         float2* dst = (float2*)a.wt + base;
         tube_fwd_post_nat<N>(row, twn, t, T, [&](int b, float re, float im) { dst[(size_t)b * n2] = make_float2(re, im); });
@@ -662,17 +671,25 @@ void slice_set_attr(int n3, size_t lds) {
   }
 }
 
-bool slice_hosts_pinvy(int n2, int n3) { return coop_threads(n2, n3) > 0; }
+bool slice_fused(int n2, int n3) { return slice_supported(n3) && slice_lds_bytes(n2, n3) <= TCTF_SLICE_LDS_MAX; }
+
+bool slice_hosts_pinvy(int n2, int n3) { return slice_fused(n2, n3) && coop_threads(n2, n3) > 0; }
 
 size_t slice_launch_lds_bytes(int n2, int n3, int r) {
+  if (!slice_fused(n2, n3)) return 0;
   const size_t a = slice_lds_bytes(n2, n3), b = slice_hosts_pinvy(n2, n3) ? pinvy_lds_bytes(r) : 0;
   return a > b ? a : b;
 }
 
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g) {
+  if (!slice_fused(p.n2, p.n3)) {
+    launch_slice_generic(p, mode, w_out, z_out, w_from_g);
+    return;
+  }
   SliceArgs a;
   a.npinv = (mode == SLICE_ITER && slice_hosts_pinvy(p.n2, p.n3)) ? p.nb : 0;
   a.pa = pinvy_args(p);
+  a.ctr = p.ctr;
   a.zt = p.zt;
   a.gp = p.gp;
   a.wtab = p.wtab;

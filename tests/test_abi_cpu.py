@@ -42,9 +42,9 @@ def test_default_params_and_status_strings():
     (dict(n1=0, n2=4, n3=4, r=1), -2),
     (dict(n1=8, n2=4, n3=4, r=5), -2),          # r > min(n1, n2)
     (dict(n1=8, n2=40, n3=40, r=33), -2),       # r > 32
-    (dict(n1=8, n2=4, n3=17, r=2), -2),         # unsupported tube length
+    (dict(n1=8, n2=4, n3=9000, r=2), -2),       # tube length above the limit
     (dict(n1=9000, n2=4, n3=4, r=2), -2),       # n1 above the limit
-    (dict(n1=8, n2=1000, n3=128, r=2), -2),     # slice does not fit LDS
+    (dict(n1=8, n2=1100, n3=16, r=2), -2),      # n2 above the limit
     (dict(n1=8, n2=4, n3=4, r=2, mu=-1.0), -1),
     (dict(n1=8, n2=4, n3=4, r=2, rho2=float("nan")), -1),
     (dict(n1=8, n2=4, n3=4, r=2, eta=2.0), -1),

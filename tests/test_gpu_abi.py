@@ -83,17 +83,22 @@ def test_complete_one_call():
     assert abs(f0 - info["f0"][-1]) / info["f0"][-1] < 1e-5
 
 
-def test_mixed_precision_tracks_fp32():
-    """BF16 storage of W~ and BF16 slice-product operands: the completion error stays close
-    to the FP32 path (reported in detail by the bench's equal-error protocol)."""
-    w, d = make_workload("od36x48x7_r3")
-    a = gpu_run(d, w.r, w.iters)
-    b = gpu_run(d, w.r, w.iters, precision="mixed")
+@pytest.mark.parametrize("name", ["od529x96x112_r16", "od36x48x7_r3"])
+def test_mixed_precision_reaches_the_fp32_error(name):
+    """W~ stored in BF16 (stochastic rounding), products accumulated in FP32: after the
+    workload's whole run the completion error (RSE against the full synthetic tensor) is
+    within the relative gap 5e-3 of the FP32 run's.  Runs are deterministic."""
+    w, d = make_workload(name)
+    iters = 200 if name.startswith("od529") else w.iters
+    a = gpu_run(d, w.r, iters)
+    b = gpu_run(d, w.r, iters, precision="mixed")
+    b2 = gpu_run(d, w.r, iters, precision="mixed")
     rse_a = oracle.rse(a["W"], d["M"])
     rse_b = oracle.rse(b["W"], d["M"])
-    print(f"RSE fp32 {rse_a:.5f} mixed {rse_b:.5f} W rel diff {rel(b['W'], a['W']):.2e}", flush=True)
+    print(f"{name} {iters} it: RSE fp32 {rse_a:.6f} mixed {rse_b:.6f} gap {rse_b / rse_a - 1:+.2e}", flush=True)
     assert np.all(np.isfinite(b["W"]))
-    assert abs(rse_b - rse_a) <= 0.05 * rse_a
+    assert abs(rse_b / rse_a - 1.0) <= 5e-3
+    assert np.array_equal(b["W"], b2["W"])
 
 
 def test_stage_profile_records_each_launch():

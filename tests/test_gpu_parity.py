@@ -252,3 +252,32 @@ def test_two_row_groups_through_graph_replays():
     g = gpu_run(d, 3, 23)
     st, info = oracle_run(d, 3, 23, history=False)
     _compare(g, st, info, label="300x14x5 r3, 23 iterations")
+
+
+@pytest.mark.parametrize("n1,n2,n3,r,p", [
+    (20, 15, 17, 3, 0.4),     # odd tube length outside the generated transform lengths
+    (12, 10, 144, 3, 0.5),    # 144: the OD count as the tube (slot x day x OD layout)
+    (11, 11, 1008, 3, 0.5),   # 11 x 11 x 1008: the router-pair layout of the paper's Abilene tensor
+    (8, 300, 128, 2, 0.4),    # a generated length whose slice is larger than the fused kernel's LDS
+])
+def test_three_launch_slice_path(n1, n2, n3, r, p):
+    """Steps 3, 4 and 7 through the spatial buffers (direct tube transforms) against the
+    oracle: W, Z, f0, and the stationarity measures (W-KKT maxima) of the same path."""
+    d = make_inputs(n1, n2, n3, r, p=p, seed=n1 * n2 + n3, weekly=True, sigma_od=1.0, noise=0.02)
+    g = gpu_run(d, r, 8)
+    st, info = oracle_run(d, r, 8, history=True)
+    _compare(g, st, info, label=f"{n1}x{n2}x{n3} r{r} (three-launch slice)")
+    s = g["ctx"].stationarity()
+    so = oracle.stationarity(info["problem"], st)
+    assert abs(s[0] - so["factor"]) <= 1e-3 * so["factor"] + 1e-7, (s, so)
+    assert s[1] < 1e-5 and s[2] == 0.0
+
+
+def test_three_launch_slice_path_mixed_precision():
+    """BF16 W~ (stochastic rounding) on the three-launch path: deterministic and close to FP32."""
+    d = make_inputs(12, 10, 144, 3, p=0.5, seed=1234, weekly=True, sigma_od=1.0, noise=0.02)
+    a = gpu_run(d, 3, 30)
+    b = gpu_run(d, 3, 30, precision="mixed")
+    c = gpu_run(d, 3, 30, precision="mixed")
+    assert np.array_equal(b["W"], c["W"])
+    assert rel(b["W"], a["W"]) < 1e-2
