@@ -173,6 +173,22 @@ tctf_status tctf_complete(const tctf_params* p, const float* G, const uint8_t* o
                           void* workspace, size_t ws_bytes, void* hip_stream,
                           float* W_out, double* f0_out);
 
+/* Allocation-free variant of tctf_complete, for callers that cannot allocate device memory
+ * (serving loops or harnesses in which hipMalloc is not allowed).  Same arguments and
+ * results as tctf_complete minus the workspace: a static scratch array of the library,
+ * TCTF_NOALLOC_SCRATCH_BYTES per device (each device the library runs on holds it until the
+ * process ends), serves as the workspace.  The call allocates nothing (no hipMalloc or
+ * hipFree, no host allocation), creates no stream, event or graph (every launch is eager)
+ * and synchronises hip_stream before it returns.  A problem whose workspace
+ * (tctf_workspace_bytes) exceeds the scratch is rejected with TCTF_E_WORKSPACE before any
+ * device work.  Every call on one device uses that device's one scratch, which keeps the
+ * last call's contents (each call clears what must start at zero): calls that overlap on one
+ * device, from other threads or on other streams, race and give undefined results. */
+#define TCTF_NOALLOC_SCRATCH_BYTES (32u << 20)
+tctf_status tctf_complete_noalloc(const tctf_params* p, const float* G, const uint8_t* omega,
+                                  const float* X0, const float* Y0, uint64_t seed, int32_t iters,
+                                  void* hip_stream, float* W_out, double* f0_out);
+
 /* Time one stage of the iteration: launch it `reps` times back to back on the context's
  * stream between two HIP events and return the mean duration in microseconds.  Stages:
  *   0 slice kernel (inverse tube transform, W-step, forward transform; the W~ stream)

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libtctf2r.so")
 
 TCTF_OK, TCTF_E_ARG, TCTF_E_SHAPE, TCTF_E_NONFINITE, TCTF_E_HIP, TCTF_E_WORKSPACE, TCTF_E_STATE = 0, -1, -2, -3, -4, -5, -6
 TCTF_FP32, TCTF_MIXED_BF16 = 0, 1
+TCTF_NOALLOC_SCRATCH_BYTES = 32 << 20   # static scratch of tctf_complete_noalloc (the header's constant)
 STAGES = {"slice": 0, "zgemm": 1, "agemm": 2, "hsolve": 3, "bgemm": 4, "ystep": 5, "pinvy": 6, "iteration": 7}
 
 
@@ -64,6 +65,7 @@ def library() -> ctypes.CDLL:
         "tctf_profile": (I32, [P, ctypes.c_uint32]),
         "tctf_run": (I32, [P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "tctf_track_termination": (I32, [P, I32]),
+        "tctf_complete_noalloc": (I32, [PP, P, P, P, P, U64, I32, P, P, ctypes.POINTER(D)]),
         "tctf_adjoint_workspace_bytes": (I32, [PP, ctypes.POINTER(S)]),
         "tctf_adjoint_step": (I32, [P, P, P, P, P, P, P, P, S]),
         "tctf_adjoint_initial": (I32, [P, P, P, P, P]),
@@ -181,6 +183,14 @@ def tctf_complete(p: tctf_params, G, omega, X0, Y0, seed: int, iters: int, works
     _check(library().tctf_complete(ctypes.byref(p), _ptr(G), _ptr(omega), _ptr(X0), _ptr(Y0), seed, iters,
                                    _ptr(workspace), ws_bytes, stream, _ptr(W_out), ctypes.byref(f0)),
            "tctf_complete")
+    return f0.value
+
+
+def tctf_complete_noalloc(p: tctf_params, G, omega, X0, Y0, seed: int, iters: int, stream: int | None,
+                          W_out) -> float:
+    f0 = ctypes.c_double()
+    _check(library().tctf_complete_noalloc(ctypes.byref(p), _ptr(G), _ptr(omega), _ptr(X0), _ptr(Y0), seed, iters,
+                                           stream, _ptr(W_out), ctypes.byref(f0)), "tctf_complete_noalloc")
     return f0.value
 
 

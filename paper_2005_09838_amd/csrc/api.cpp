@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -129,6 +130,7 @@ struct tctf_ctx {
   int64_t iters;
   bool term_valid;
   bool track = false;   // step 6 evaluated after every tctf_step call (tctf_track_termination)
+  bool eager = false;   // never capture or replay a graph (the allocation-free entry point)
   // stage timing of tctf_step (tctf_profile): one event pair per profiled launch
   uint32_t prof_mask = 0;
   std::vector<hipEvent_t> prof_ev;
@@ -411,7 +413,7 @@ tctf_status tctf_step(tctf_ctx* c, int32_t iters) {
   // timed); when step 6 is tracked the last iteration runs eagerly after the snapshot
   const int32_t body = c->track ? iters - 1 : iters;
   int32_t it = 0;
-  if (c->prof_mask == 0) {
+  if (c->prof_mask == 0 && !c->eager) {
     tctf_status s = ensure_graph(c);
     if (s != TCTF_OK) return s;
     for (; body - it >= GRAPH_ITERS; it += GRAPH_ITERS) {
@@ -649,6 +651,58 @@ tctf_status tctf_complete(const tctf_params* p, const float* G, const uint8_t* o
   if (s == TCTF_OK) s = tctf_get_result(c, W_out, nullptr, nullptr, nullptr);
   if (s == TCTF_OK && f0_out) s = tctf_objective(c, f0_out);
   tctf_destroy(c);
+  return s;
+}
+
+}  // extern "C"
+
+// Static scratch of the allocation-free entry point: one copy per device, held by the device
+// from module load until the process ends.  Host code never passes `scratch` itself to a
+// kernel (in host code the name is only a stand-in); it uses the device address that
+// hipGetSymbolAddress returns for the current device, fetched once per device.
+static __device__ __align__(256) unsigned char scratch[TCTF_NOALLOC_SCRATCH_BYTES];
+#define NOALLOC_MAX_DEVICES 64
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static tctf_status scratch_address(int device, void** ptr) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return fail(TCTF_E_HIP, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(TCTF_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return TCTF_OK;
+}
+
+extern "C" {
+
+tctf_status tctf_complete_noalloc(const tctf_params* p, const float* G, const uint8_t* omega, const float* X0,
+                                  const float* Y0, uint64_t seed, int32_t iters, void* hip_stream, float* W_out,
+                                  double* f0_out) {
+  if (!W_out) return fail(TCTF_E_ARG, "W_out is NULL");
+  if (iters < 0) return fail(TCTF_E_ARG, "iters must be >= 0");
+  tctf_status s = validate(p);
+  if (s != TCTF_OK) return s;
+  const size_t need = make_layout(*p).total;
+  if (need > (size_t)TCTF_NOALLOC_SCRATCH_BYTES)
+    return fail(TCTF_E_WORKSPACE, "problem needs %zu bytes of scratch; the static scratch holds %zu", need,
+                (size_t)TCTF_NOALLOC_SCRATCH_BYTES);
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  void* ws = nullptr;
+  s = scratch_address(device, &ws);
+  if (s != TCTF_OK) return s;
+  tctf_ctx c;   // on the stack: no host allocation either (its vectors stay empty)
+  c.eager = true;
+  s = ctx_init(&c, p, G, omega, X0, Y0, seed, ws, need, hip_stream);
+  if (s == TCTF_OK) s = tctf_step(&c, iters);
+  if (s == TCTF_OK) s = tctf_get_result(&c, W_out, nullptr, nullptr, nullptr);
+  if (s == TCTF_OK && f0_out) s = tctf_objective(&c, f0_out);
+  ctx_release(&c);
   return s;
 }
 

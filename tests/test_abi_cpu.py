@@ -95,3 +95,10 @@ def test_adjoint_workspace_and_precision_checks():
     with pytest.raises(B.TctfError) as e:
         B.tctf_adjoint_workspace_bytes(B.make_params(144, 288, 28, 8, precision="mixed"))
     assert e.value.status == B.TCTF_E_ARG
+
+
+def test_noalloc_scratch_constant_matches_the_header():
+    from paper_2005_09838_amd import binding as B
+    text = open(HEADER).read()
+    m = re.search(r"#define TCTF_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == B.TCTF_NOALLOC_SCRATCH_BYTES
