@@ -19,6 +19,10 @@ roofline of the dominant kernel, the FP64 CPU oracle baseline, per-precision det
 
   --copy-calibration MIB   instead: run a plain device copy of MIB MiB five times (the
                            reference kernel that scales the FETCH_SIZE / WRITE_SIZE counters)
+  --layouts                instead: the 144 x 288 x 28 workload at each sampling rate in three
+                           layouts (OD x slot x day; the paper's slot x day x OD; origin x
+                           destination x time, 12 x 12 x 8064), --rse-iters iterations each:
+                           RSE, NMAE on the missing entries and iterations/s per layout
   --batch COUNT            instead: COUNT uneven completions (synth.batch_specs) run for
                            --steps iterations one after another and then as one batch
                            (tctf_batch_*), printing one JSON line with both aggregate rates
@@ -189,6 +193,46 @@ def batch_bench(count, steps, warmup):
     print(json.dumps(line), flush=True)
 
 
+def layout_bench(iters, rates):
+    """Completion error and speed of one data set in three layouts (section 3.1 models the
+    traffic as slot x day x OD; the experiments of section 5 use origin x destination x
+    time).  The synthetic generator builds its low-rank structure in the OD x slot x day
+    layout, so that layout is favoured by construction; the comparison shows how much the
+    mode roles (H along mode 1, K along mode 2, the transform along mode 3) matter."""
+    import numpy as np
+    import torch
+    from paper_2005_09838_amd import Completion
+    from synth import LAYOUTS, make_workload, relayout
+    import oracle
+    dev = torch.device("cuda:0")
+    rows = []
+    for p in rates:
+        w, d = make_workload(f"od144x288x28_r8_p{p}")
+        for name in LAYOUTS:
+            e = relayout(d, name, w.r, w.seed)
+            t = lambda a: torch.from_numpy(a).to(dev)
+            c = Completion(t(e["G"]), t(e["omega"]), w.r, mu=w.mu, rho1=w.rho1, rho2=w.rho2, X0=t(e["X0"]),
+                           Y0=t(e["Y0"]))
+            c.step(1)   # graph capture outside the timed run
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.step(iters - 1)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            W = c.result()["W"].cpu().numpy().astype(np.float64)
+            c.close()
+            M, om = e["M"].astype(np.float64), e["omega"]
+            rows.append({"p": p / 100, "layout": name, "shape": list(e["M"].shape),
+                         "rse": oracle.rse(W, M), "rse_missing": oracle.rse(W, M, 1 - om),
+                         "nmae_missing": oracle.nmae(W, M, om), "iters_per_s": (iters - 1) / dt})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    base = {r["p"]: r for r in rows if r["layout"] == "od_slot_day"}
+    for r in rows:
+        r["nmae_vs_od_slot_day"] = r["nmae_missing"] / base[r["p"]]["nmae_missing"]
+    print(json.dumps({"metric": "completion error and iters/s of the 144x288x28 workload per layout",
+                      "iterations": iters, "rows": rows}), flush=True)
+
+
 def copy_calibration(mib):
     """A plain elementwise device copy of `mib` MiB (read once, written once), five times."""
     import torch
@@ -250,8 +294,11 @@ def cpu_baseline(d, w, iters, iters_all):
             prob = oracle.Problem(d["G"], d["omega"], w.r, w.mu, w.rho1, w.rho2)
             st = oracle.initial_state(prob, d["X0"], d["Y0"])
             t0 = time.perf_counter()
-            for _ in range(n):
+            for k in range(n):
                 st = oracle.iterate(prob, st)
+                if (k + 1) % 10 == 0:
+                    print(f"oracle ({label}): {k + 1}/{n} iterations, {time.perf_counter() - t0:.1f} s",
+                          file=sys.stderr, flush=True)
             dt = time.perf_counter() - t0
         out[label] = {"iters_per_s": n / dt, "cores": threads, "seconds": dt, "iters": n, "state": st}
     return out
@@ -284,6 +331,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT")
+    ap.add_argument("--layouts", action="store_true")
     ap.add_argument("--only", choices=("fp32", "mixed"), default=None,
                     help="run one precision (no equal-error comparison); for counter runs")
     args = ap.parse_args()
@@ -296,6 +344,9 @@ def main():
         return
     if args.batch:
         batch_bench(args.batch, args.steps, args.warmup)
+        return
+    if args.layouts:
+        layout_bench(args.rse_iters, (10, 20, 40, 60, 80))
         return
 
     import numpy as np

@@ -77,6 +77,14 @@ typedef struct {
   int32_t pinv_mode;    /* 0: inverse by elimination when the Gram provably keeps every
                            eigenvalue, eigen-decomposition otherwise; 1: always eigen     */
   double eps;           /* threshold of the termination test (step 6), default 1e-6        */
+  double rank_tol;      /* step 5: keep in each stored frequency the components of
+                           Z~_k = X~_k Y~_k whose singular values exceed rank_tol times the
+                           largest over all frequencies; >= 0, default 0                  */
+  int32_t rank_every;   /* step 5 runs after iterations rank_every, 2 rank_every, ...;
+                           0 (default) = never, the rank vector stays r everywhere.  With
+                           rank_every > 0 iterations are launched eagerly (no graph replay)
+                           and batches refuse the context                                   */
+  int32_t reserved;     /* 0 */
 } tctf_params;
 /* Sizes: n1 <= 8192, n2 <= 1024, n3 <= 8192.  For n3 in 1..16, 20, 24, 28, 32, 40, 48, 56,
  * 64, 84, 96, 112, 128 (the lengths the tube transform is generated for) with one slice
@@ -160,6 +168,14 @@ tctf_status tctf_get_result(tctf_ctx* c, float* W, float* Z, float* X, float* Y)
 tctf_status tctf_state_bytes(tctf_ctx* c, size_t* bytes);
 tctf_status tctf_get_state(tctf_ctx* c, void* dst, size_t bytes);
 tctf_status tctf_set_state(tctf_ctx* c, const void* src, size_t bytes);
+
+/* Synchronise and copy the rank vector of step 5 (algorithm box: r^(l+1), one rank per
+ * frequency) to the HOST array ranks[nb], nb = n3 / 2 + 1 stored frequencies (the others
+ * mirror them).  r everywhere until step 5 has run.  Step 5 (tctf_params.rank_tol,
+ * rank_every) rotates each frequency's factors into the singular basis of Z~_k, computed
+ * from the r x r Grams in FP64, and zeroes the dropped components; f0's fit, ridge and K
+ * terms after an adjusting iteration are those of its W-step (taken before the truncation). */
+tctf_status tctf_rank_vector(tctf_ctx* c, int32_t* ranks);
 
 /* Iterations run since create (or as restored). */
 tctf_status tctf_iterations(tctf_ctx* c, int64_t* iters);

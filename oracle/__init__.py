@@ -19,7 +19,7 @@ invariants and brute force; see the design notes for the list of pins.
 """
 from . import adjoint, algorithm, model, tensor_algebra
 from .algorithm import (Problem, State, complete, initial_state, iterate, nmae, objective,
-                        pinv_h, rse, stationarity, termination, x_update, y_update, z_of)
+                        pinv_h, rank_adjust, rse, stationarity, termination, x_update, y_update, z_of)
 from .model import (h_rho1, k_mu_rho2, objective_fourier, objective_spatial, w_kkt_residual,
                     w_step, w_step_closed_form)
 from .tensor_algebra import (bcirc, bvec, bvfold, dft3, dft3_by_sum, fold, idft3, toeplitz_diff,
@@ -27,7 +27,7 @@ from .tensor_algebra import (bcirc, bvec, bvfold, dft3, dft3_by_sum, fold, idft3
 
 __all__ = [
     "adjoint", "algorithm", "model", "tensor_algebra", "Problem", "State", "complete", "initial_state",
-    "iterate", "nmae", "objective", "pinv_h", "rse", "stationarity", "termination", "x_update",
+    "iterate", "nmae", "objective", "pinv_h", "rank_adjust", "rse", "stationarity", "termination", "x_update",
     "y_update", "z_of", "h_rho1", "k_mu_rho2", "objective_fourier", "objective_spatial",
     "w_kkt_residual", "w_step", "w_step_closed_form", "bcirc", "bvec", "bvfold", "dft3",
     "dft3_by_sum", "fold", "idft3", "toeplitz_diff", "tprod", "tprod_definition", "tubal_rank",

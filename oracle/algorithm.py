@@ -156,6 +156,38 @@ def iterate(prob: Problem, st: State, check_symmetry: bool = True) -> State:
     return State(xt_new, yt_new, w, wt, st.it + 1)
 
 
+def rank_adjust(prob: Problem, st: State, tol: float):
+    """Step 5 of the algorithm box (adjust the rank vector r^(l+1) and the sizes of X~_k,
+    Y~_k) under this build's rule, which the paper leaves open: in every frequency k keep the
+    components of Z~_k = X~_k Y~_k whose singular values exceed tol times the largest singular
+    value over all frequencies.  With the SVD Z~_k = U S V^*, the kept part is written as
+    X~_k = U_q S_q, Y~_k = V_q^* in the first q = r_k columns / rows, the rest zero (the factor
+    sizes stay r; the zero part is what "the size" r_k leaves out).  Frequencies past m3 / 2
+    take the conjugates (eq. (rcm_3-k+2)); the real frequencies are decomposed as real
+    matrices.  Returns (state, r_k for every k)."""
+    m3 = prob.shape[2]
+    r = prob.r
+    zt = np.einsum("irk,rjk->ijk", st.xt, st.yt)
+    real = lambda k: k == 0 or (m3 % 2 == 0 and k == m3 // 2)
+    svd = lambda k: np.linalg.svd(zt[:, :, k].real if real(k) else zt[:, :, k], full_matrices=False)
+    smax = max(float(np.linalg.svd(zt[:, :, k], compute_uv=False)[0]) for k in range(m3))
+    xt = np.zeros_like(st.xt)
+    yt = np.zeros_like(st.yt)
+    ranks = np.zeros(m3, dtype=int)
+    for k in range(m3 // 2 + 1):
+        u, sv, vh = svd(k)
+        q = int(np.sum(sv[:r] > tol * smax))
+        xt[:, :q, k] = u[:, :q] * sv[:q]
+        yt[:q, :, k] = vh[:q]
+        ranks[k] = q
+        kc = (m3 - k) % m3
+        if kc != k:
+            xt[:, :, kc] = np.conj(xt[:, :, k])
+            yt[:, :, kc] = np.conj(yt[:, :, k])
+            ranks[kc] = q
+    return State(xt, yt, st.w, st.wt, st.it), ranks
+
+
 def z_of(st: State) -> np.ndarray:
     """Z = X * Y of the state (real part of the inverse transform of X~_k Y~_k)."""
     return idft3(np.einsum("irk,rjk->ijk", st.xt, st.yt)).real
@@ -195,22 +227,27 @@ def stationarity(prob: Problem, st: State) -> dict:
 
 
 def complete(g, omega_mask, r, x0, y0, iters, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0,
-             record_objective=False):
+             record_objective=False, rank_tol=0.0, rank_every=0):
     """Run ``iters`` iterations of TCTF2R from (X0, Y0, W0 = P_Omega(G)).
 
-    Returns (state, info) where info holds the objective history if requested
-    (f0 before the first iteration, then after each).
+    With rank_every > 0, step 5 (:func:`rank_adjust` with ``rank_tol``) runs after
+    iterations rank_every, 2 rank_every, ...  Returns (state, info) where info holds the
+    objective history if requested (f0 before the first iteration, then after each) and the
+    last rank vector.
     """
     prob = Problem(g, omega_mask, r, mu, rho1, rho2, eta)
     st = initial_state(prob, x0, y0)
     hist = []
+    ranks = np.full(prob.shape[2], r)
     if record_objective:
         hist.append(objective(prob, st))
     for _ in range(iters):
         st = iterate(prob, st)
+        if rank_every > 0 and st.it % rank_every == 0:
+            st, ranks = rank_adjust(prob, st, rank_tol)
         if record_objective:
             hist.append(objective(prob, st))
-    return st, {"f0": hist, "problem": prob}
+    return st, {"f0": hist, "problem": prob, "ranks": ranks}
 
 
 def rse(w: np.ndarray, m: np.ndarray, mask: np.ndarray | None = None) -> float:

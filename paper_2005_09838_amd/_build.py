@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtctf2r.so")
 SOURCES = ["api.cpp", "kernels_setup.hip", "kernels_slice.hip", "kernels_gemm.hip", "kernels_solve.hip",
            "kernels_check.hip", "kernels_adjoint.hip",
-           "kernels_slice_generic.hip"]
+           "kernels_slice_generic.hip", "kernels_rank.hip"]
 ARCH = os.environ.get("TCTF_OFFLOAD_ARCH", "gfx950")
 
 

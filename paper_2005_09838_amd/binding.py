@@ -23,7 +23,8 @@ class tctf_params(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32), ("r", ctypes.c_int32),
                 ("mu", ctypes.c_double), ("rho1", ctypes.c_double), ("rho2", ctypes.c_double),
                 ("eta", ctypes.c_double), ("precision", ctypes.c_int32), ("pinv_mode", ctypes.c_int32),
-                ("eps", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("rank_tol", ctypes.c_double), ("rank_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class TctfError(RuntimeError):
@@ -59,6 +60,7 @@ def library() -> ctypes.CDLL:
         "tctf_get_state": (I32, [P, P, S]),
         "tctf_set_state": (I32, [P, P, S]),
         "tctf_iterations": (I32, [P, ctypes.POINTER(I64)]),
+        "tctf_rank_vector": (I32, [P, ctypes.POINTER(I32)]),
         "tctf_destroy": (None, [P]),
         "tctf_complete": (I32, [PP, P, P, P, P, U64, I32, P, S, P, P, ctypes.POINTER(D)]),
         "tctf_time_stage": (I32, [P, I32, I32, ctypes.POINTER(D)]),
@@ -167,6 +169,12 @@ def tctf_set_state(ctx, src, nbytes: int):
     _check(library().tctf_set_state(ctx, _ptr(src), nbytes), "tctf_set_state")
 
 
+def tctf_rank_vector(ctx, nb: int) -> list:
+    v = (ctypes.c_int32 * nb)()
+    _check(library().tctf_rank_vector(ctx, v), "tctf_rank_vector")
+    return list(v)
+
+
 def tctf_iterations(ctx) -> int:
     v = ctypes.c_int64()
     _check(library().tctf_iterations(ctx, ctypes.byref(v)), "tctf_iterations")
@@ -252,7 +260,7 @@ def tctf_last_error() -> str:
 # ---------------------------------------------------------------- torch convenience layer
 
 def make_params(n1, n2, n3, r, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision="fp32", pinv_mode=0,
-                eps=1e-6) -> tctf_params:
+                eps=1e-6, rank_tol=0.0, rank_every=0) -> tctf_params:
     p = tctf_default_params()
     p.n1, p.n2, p.n3, p.r = int(n1), int(n2), int(n3), int(r)
     p.mu, p.rho1, p.rho2, p.eta = float(mu), float(rho1), float(rho2), float(eta)
@@ -260,6 +268,8 @@ def make_params(n1, n2, n3, r, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision
         if isinstance(precision, str) else int(precision)
     p.pinv_mode = int(pinv_mode)
     p.eps = float(eps)
+    p.rank_tol = float(rank_tol)
+    p.rank_every = int(rank_every)
     return p
 
 
@@ -287,7 +297,7 @@ class Completion:
         return self
 
     def __init__(self, G, omega, r, *, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision="fp32",
-                 pinv_mode=0, eps=1e-6, X0=None, Y0=None, seed=0, stream=None):
+                 pinv_mode=0, eps=1e-6, X0=None, Y0=None, seed=0, stream=None, rank_tol=0.0, rank_every=0):
         import torch
         self._owned = True
         if not (G.is_cuda and omega.is_cuda):
@@ -298,7 +308,8 @@ class Completion:
         self.omega = omega.contiguous().to(torch.uint8)
         self.X0 = None if X0 is None else X0.contiguous().to(torch.float32)
         self.Y0 = None if Y0 is None else Y0.contiguous().to(torch.float32)
-        self.params = make_params(n1, n2, n3, r, mu, rho1, rho2, eta, precision, pinv_mode, eps)
+        self.params = make_params(n1, n2, n3, r, mu, rho1, rho2, eta, precision, pinv_mode, eps, rank_tol,
+                                  rank_every)
         self.shape = (n1, n2, n3)
         self.r = r
         self.stream = stream
@@ -345,6 +356,10 @@ class Completion:
 
     def stationarity(self):
         return tctf_stationarity(self.ctx)
+
+    def rank_vector(self):
+        """Step 5's rank vector r_b of the stored frequencies b = 0 .. n3 / 2."""
+        return tctf_rank_vector(self.ctx, self.shape[2] // 2 + 1)
 
     @property
     def iterations(self):

@@ -51,7 +51,7 @@ struct StateHeader {
 
 struct Layout {
   size_t gp, wt, zt, xt, yt, rhs, bpart, gxm, dmat, gxp, qx, qx_zero, gym, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
-      flag, ctr, zsp, wsp, csp, twg, scal, xt_prev, yt_prev, wt_prev, stat_work, kkt, total;
+      flag, ctr, zsp, wsp, csp, twg, rsig, rtx, rty, ranks, scal, xt_prev, yt_prev, wt_prev, stat_work, kkt, total;
   size_t state_bytes;
 };
 
@@ -87,7 +87,7 @@ static Layout make_layout(const tctf_params& p) {
   L.xt = take(nb * r * n1 * 8);
   L.yt = take(nb * r * n2 * 8);
   L.rhs = take(nb * r * n1 * 8);
-  L.bpart = take(nb * nchunk * r * n2 * 8);
+  L.bpart = take(nb * nchunk * r * n2 * 16);
   L.gxm = take(nb * r * r * 16);
   L.dmat = take(nb * r * r * 16);
   L.gxp = take(nb * r * r * 16);
@@ -108,6 +108,10 @@ static Layout make_layout(const tctf_params& p) {
   L.wsp = take(gen ? n1 * n2 * n3 * 4 : 0);
   L.csp = take(gen ? n1 * n2 * n3 * 4 : 0);
   L.twg = take(gen ? n3 * 16 : 0);
+  L.rsig = take(nb * r * 8);
+  L.rtx = take(nb * r * r * 16);
+  L.rty = take(nb * r * r * 16);
+  L.ranks = take(nb * 4);
   L.scal = take(16 * 8);
   L.xt_prev = take(nb * r * n1 * 8);
   L.yt_prev = take(nb * r * n2 * 8);
@@ -117,7 +121,7 @@ static Layout make_layout(const tctf_params& p) {
   L.kkt = take(n1 * 3 * 8);
   L.total = o;
   L.state_bytes = sizeof(StateHeader) + nb * r * n1 * 8 + nb * r * n2 * 8 + n1 * nb * n2 * welem +
-                  2 * nb * r * r * 16 + nb * 4 + n1 * 3 * 8 + nb * 8 + 4;
+                  2 * nb * r * r * 16 + nb * 4 + n1 * 3 * 8 + nb * 8 + 4 + nb * 4;
   return L;
 }
 
@@ -160,6 +164,8 @@ static tctf_status validate(const tctf_params* p) {
   if (p->precision != TCTF_FP32 && p->precision != TCTF_MIXED_BF16) return fail(TCTF_E_ARG, "unknown precision %d", p->precision);
   if (p->pinv_mode != 0 && p->pinv_mode != 1) return fail(TCTF_E_ARG, "pinv_mode must be 0 or 1");
   if (!(p->eps >= 0.0)) return fail(TCTF_E_ARG, "eps must be >= 0");
+  if (!(std::isfinite(p->rank_tol) && p->rank_tol >= 0.0)) return fail(TCTF_E_ARG, "rank_tol must be finite and >= 0");
+  if (p->rank_every < 0) return fail(TCTF_E_ARG, "rank_every must be >= 0");
   return TCTF_OK;
 }
 
@@ -210,7 +216,7 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.xt = (float2*)(w + L.xt);
   q.yt = (float2*)(w + L.yt);
   q.rhs = (float2*)(w + L.rhs);
-  q.bpart = (float2*)(w + L.bpart);
+  q.bpart = (double2*)(w + L.bpart);
   q.gxm = (cd*)(w + L.gxm);
   q.dmat = (cd*)(w + L.dmat);
   q.gxp = (cd*)(w + L.gxp);
@@ -230,6 +236,10 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.wsp = (float*)(w + L.wsp);
   q.csp = (float*)(w + L.csp);
   q.twg = (double2*)(w + L.twg);
+  q.rsig = (double*)(w + L.rsig);
+  q.rtx = (cd*)(w + L.rtx);
+  q.rty = (cd*)(w + L.rty);
+  q.ranks = (int*)(w + L.ranks);
   q.scal = (double*)(w + L.scal);
   q.xt_prev = (float2*)(w + L.xt_prev);
   q.yt_prev = (float2*)(w + L.yt_prev);
@@ -276,6 +286,10 @@ static tctf_status enqueue_iteration(tctf_ctx* c) {
   // cooperative slice launch, or of this launch where the slice runs the per-thread kernel
   if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p, tctf::slice_hosts_pinvy(p.n2, p.n3) ? 0 : 1); });
   if (s == TCTF_OK) s = stage(c, 0, [&] { tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0); });
+  // step 5 after iterations rank_every, 2 rank_every, ... (c->iters counts the iterations
+  // before this one; such contexts never replay graphs, so the count is exact)
+  if (s == TCTF_OK && c->prm.rank_every > 0 && (c->iters + 1) % c->prm.rank_every == 0)
+    tctf::launch_rank_adjust(p, c->prm.rank_tol);
   if (s != TCTF_OK) return s;
   return check_launch();
 }
@@ -309,6 +323,8 @@ static tctf_status ctx_init(tctf_ctx* c, const tctf_params* prm, const float* G,
   tctf::zgemm_set_attr(p.r);
   tctf::launch_zero(p, p.flag, 64);
   tctf::launch_zero(p, p.ctr, 64);
+  tctf::launch_rank_init(p);
+  tctf::rank_set_attr(p.r);
   tctf::launch_zero(p, p.qy_zero, (size_t)p.nb * 4);
   tctf::launch_pack_g(p, G, omega);
   tctf::launch_tables(p);
@@ -413,7 +429,7 @@ tctf_status tctf_step(tctf_ctx* c, int32_t iters) {
   // timed); when step 6 is tracked the last iteration runs eagerly after the snapshot
   const int32_t body = c->track ? iters - 1 : iters;
   int32_t it = 0;
-  if (c->prof_mask == 0 && !c->eager) {
+  if (c->prof_mask == 0 && !c->eager && c->prm.rank_every == 0) {
     tctf_status s = ensure_graph(c);
     if (s != TCTF_OK) return s;
     for (; body - it >= GRAPH_ITERS; it += GRAPH_ITERS) {
@@ -546,6 +562,7 @@ static int state_regions(tctf_ctx* c, Region* r) {
   r[n++] = {L.slice_obj, (size_t)p.n1 * 3 * 8};
   r[n++] = {L.bin_obj, (size_t)p.nb * 8};
   r[n++] = {L.ctr, 4};
+  r[n++] = {L.ranks, (size_t)p.nb * 4};
   return n;
 }
 
@@ -598,6 +615,13 @@ tctf_status tctf_set_state(tctf_ctx* c, const void* src, size_t bytes) {
   HIP_TRY(hipStreamSynchronize(p.stream));
   c->iters = h.iters;
   c->term_valid = false;
+  return TCTF_OK;
+}
+
+tctf_status tctf_rank_vector(tctf_ctx* c, int32_t* ranks) {
+  if (!c || !ranks) return fail(TCTF_E_ARG, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(ranks, c->plan.ranks, (size_t)c->plan.nb * 4, hipMemcpyDeviceToHost, c->plan.stream));
+  HIP_TRY(hipStreamSynchronize(c->plan.stream));
   return TCTF_OK;
 }
 
@@ -917,6 +941,10 @@ tctf_status tctf_batch_create(int32_t n, const tctf_params* p, const float* cons
   for (int32_t k = 0; k < n; ++k) {
     size_t bytes = 0;
     (void)tctf_workspace_bytes(&p[k], &bytes);
+    if (p[k].rank_every != 0) {
+      tctf_batch_destroy(b);
+      return fail(TCTF_E_ARG, "member %d: batches run step 5 never (rank_every must be 0)", k);
+    }
     tctf_ctx* c = nullptr;
     s = tctf_create(&p[k], G[k], omega[k], X0 ? X0[k] : nullptr, Y0 ? Y0[k] : nullptr, seeds ? seeds[k] : 0, w,
                     align256(bytes), hip_stream, &c);

@@ -21,7 +21,7 @@ struct Plan {
   float2* xt;       // X~ [nb][r][n1]
   float2* yt;       // Y~ [nb][r][n2]
   float2* rhs;      // right-hand side of the H_rho1 solve [nb][r][n1]
-  float2* bpart;    // partial X~^* W~ [nb][nchunk][r][n2]
+  double2* bpart;   // partial X~^* W~ [nb][nchunk][r][n2] (FP64)
   cd* gxm;          // G_X = X~^* H_rho1 X~ [nb][r][r]
   cd* dmat;         // (H X~)^* (H X~) [nb][r][r]
   cd* gxp;          // G_X^+ [nb][r][r]
@@ -43,6 +43,11 @@ struct Plan {
   float* wsp;       // [n1][n2][n3]
   float* csp;       // [n1][n2][n3]
   double2* twg;     // [n3] (cos, sin)(2 pi m / n3)
+  // step 5 (rank adjustment)
+  double* rsig;     // [nb][r] singular values of Z~_b, descending
+  cd* rtx;          // [nb][r][r] factor rotations of X~ and Y~
+  cd* rty;
+  int* ranks;       // [nb] the rank vector r_b
   double* scal;     // [16] scalar results (objective, termination, stationarity)
   float2* xt_prev;  // snapshots for the termination test
   float2* yt_prev;
@@ -88,6 +93,9 @@ void pinvy_set_attr(int r);
 void zgemm_set_attr(int r);
 void launch_objective(const Plan& p);
 void launch_termination(const Plan& p);
+void launch_rank_init(const Plan& p);
+void launch_rank_adjust(const Plan& p, double tol);
+void rank_set_attr(int r);
 size_t termination_work_doubles();   // partials of the step-6 reduction held in stat_work
 void launch_stationarity(const Plan& p, int w_from_g);
 

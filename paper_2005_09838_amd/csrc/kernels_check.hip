@@ -11,7 +11,7 @@ namespace tctf {
 
 __global__ void __launch_bounds__(256) k_stat_bin(const float2* __restrict__ xt, const float2* __restrict__ yt,
                                                   const void* __restrict__ wt, const float2* __restrict__ a,
-                                                  const float2* __restrict__ bpart, const cd* __restrict__ gxm,
+                                                  const double2* __restrict__ bpart, const cd* __restrict__ gxm,
                                                   double* __restrict__ out, int n1, int n2, int n3, int r,
                                                   int nb, int nchunk, double rho1, int mixed) {
   __shared__ cd gy[TCTF_RMAX * TCTF_RMAX];
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) k_stat_bin(const float2* __restrict__ xt,
       cd_fma(v, gx[s * r + t], cd_make(y.x, y.y));
     }
     for (int c = 0; c < nchunk; ++c) {
-      const float2 bb = bpart[(((size_t)b * nchunk + c) * r + s) * n2 + j];
+      const double2 bb = bpart[(((size_t)b * nchunk + c) * r + s) * n2 + j];
       v.re -= bb.x;
       v.im -= bb.y;
     }

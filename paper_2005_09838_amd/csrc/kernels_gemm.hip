@@ -7,8 +7,8 @@
 // The complex products run on the matrix cores as real FP32 products (16 x 16 x 4 tiles):
 // a complex m x k by k x n product is an m x 2k by 2k x n' real one whose operands are the
 // interleaved (re, im) storage itself, with the signs of the complex product placed in the
-// operand that is built on the fly.  X~^* W~ is summed in FP64 over blocks of 16 rows;
-// r x r Grams and the X right-hand side epilogue are FP64.  Mixed mode reads W~ from its
+// operand that is built on the fly.  X~^* W~ runs on the FP64 matrix cores (FP64 partial
+// sums over row chunks); r x r Grams and the X right-hand side epilogue are FP64.  Mixed mode reads W~ from its
 // BF16 storage (stochastically rounded by the slice kernel) and converts to FP32 before
 // the product.
 #include <type_traits>
@@ -538,8 +538,8 @@ __device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1,
 // (X~^* W~)(s, j) = (C'[2s][2j] + C'[2s+1][2j+1], C'[2s][2j+1] - C'[2s+1][2j]).
 // Block: one chunk of at most 64 rows x one frequency.  The chunk's X~ rows and, per pass
 // of BG_COLS columns, its whole W~ slab are staged in LDS with every load of a thread
-// issued at once; each wavefront owns a quarter of the 16-column tiles of a pass.  After
-// every 16 rows the FP32 tile sums are added into FP64 accumulators.
+// issued at once; each wavefront owns a quarter of the 16-column tiles of a pass, on the
+// FP64 matrix cores.
 // At r <= 16 the first nb blocks of the launch instead form, for frequency blockIdx.x, the
 // whole Gram G_X = X~^* X~ + rho1 (H X~)^*(H X~) in FP64 on the matrix cores, its
 // pseudo-inverse and I - eta P_X (gramx_block), beside the products; at r > 16 k_gramx
@@ -549,7 +549,7 @@ __device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1,
 #define BG_WLD (2 * BG_COLS + 16)   // LDS row stride of the staged W~ slab (floats)
 template <int RM>   // r <= RM; registers and LDS allow three blocks per compute unit at r <= 16
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RM <= 16 ? 2 : 1)))
-k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, float2* __restrict__ bpart, GramOut go, int n1,
+k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, double2* __restrict__ bpart, GramOut go, int n1,
         int n2, int r, int nb, int nchunk, int chunk, int mixed) {
   extern __shared__ __align__(16) float smb[];
   constexpr bool GRAM = RM <= 16;   // at r > 16 the registers of both paths would not fit twice
@@ -612,67 +612,49 @@ k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, float2* __re
     }
     __syncthreads();
     if (j0 + BG_COLS < n2) load_slab(j0 + BG_COLS);   // the next pass's slab, in flight meanwhile
-    double dacc[MT][2][4];   // [M tile][own N tile][t]
+    // FP64 matrix-core tiles over every row of the chunk: X~ and W~ are FP32 (or BF16)
+    // values, exact in FP64, so the partial sums carry FP64 rounding only (the Y-step's
+    // G_X^{-1} amplifies any rounding of X~^* W~)
+    v4d acc[MT][2];
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < 2; ++u) acc[a][u] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; ks < nks; ++ks) {
+      const int kr = 4 * ks + q;   // chunk row of this lane's K index
+      double av[MT];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) dacc[a][u][t] = 0.0;
-    for (int kb = 0; kb < nks; kb += 4) {   // 16 rows per FP32 partial sum
-      v4f acc[MT][2];
-#pragma unroll
-      for (int a = 0; a < MT; ++a)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) acc[a][u] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int k4 = 0; k4 < 4; ++k4) {
-        const int ks = kb + k4;
-        if (ks < nks) {
-          const int kr = 4 * ks + q;   // chunk row of this lane's K index
-          float av[MT];
-#pragma unroll
-          for (int a = 0; a < MT; ++a) {
-            const int sp = 16 * a + m;   // row 2 s + d of X'
-            av[a] = (sp < 2 * r && kr < nrows) ? xs[kr * xld + sp] : 0.f;
-          }
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int nt = w + 4 * u;
-            if (nt < ntiles) {
-              const float bv = ws[kr * BG_WLD + 16 * nt + m];
-#pragma unroll
-              for (int a = 0; a < MT; ++a) acc[a][u] = mfma4(av[a], bv, acc[a][u]);
-            }
-          }
-        }
+      for (int a = 0; a < MT; ++a) {
+        const int sp = 16 * a + m;   // row 2 s + d of X'
+        av[a] = (sp < 2 * r && kr < nrows) ? (double)xs[kr * xld + sp] : 0.0;
       }
 #pragma unroll
-      for (int a = 0; a < MT; ++a)
+      for (int u = 0; u < 2; ++u) {
+        const int nt = w + 4 * u;
+        if (nt < ntiles) {
+          const double bv = (double)ws[kr * BG_WLD + 16 * nt + m];
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) dacc[a][u][t] += (double)acc[a][u][t];
+          for (int a = 0; a < MT; ++a) acc[a][u] = mfma4d(av[a], bv, acc[a][u]);
+        }
+      }
     }
-    // combine C' into (X~^* W~)(s, j): lanes m and m ^ 1 hold columns 2 j and 2 j + 1
+    // combine C' into (X~^* W~)(s, j): element t of lane (q, m) holds row 16 a + q + 4 t and
+    // column 16 nt + m of its tile, so the lanes with q and m even hold C'[2s][2j] and read
+    // C'[2s][2j+1], C'[2s+1][2j] and C'[2s+1][2j+1] from lanes + 1, + 16 and + 17
 #pragma unroll
     for (int a = 0; a < MT; ++a) {
-      {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int nt = w + 4 * u;
-          if (nt < ntiles) {
-            const int col = 16 * nt + m, j = col >> 1;
+      for (int u = 0; u < 2; ++u) {
+        const int nt = w + 4 * u;   // the same in the whole wavefront
+        if (nt < ntiles) {
+          const int j = (16 * nt + m) >> 1;
 #pragma unroll
-            for (int tp = 0; tp < 2; ++tp) {
-              // rows 2 s (t = 2 tp) and 2 s + 1 (t = 2 tp + 1) of the tile
-              const double own = dacc[a][u][2 * tp];
-              const double other = __shfl_xor(dacc[a][u][2 * tp + 1], 1);
-              const int s = (16 * a + 4 * q + 2 * tp) >> 1;
-              const double v = (m & 1) ? own - other : own + other;   // odd lane: imaginary part
-              if (s < r && j < nc)
-                ((float*)bpart)[((((size_t)b * nchunk + c) * r + s) * n2 + j0 + j) * 2 + (m & 1)] = (float)v;
-            }
+          for (int t = 0; t < 4; ++t) {
+            const double s0 = acc[a][u][t], s1 = __shfl_down(s0, 1), s16 = __shfl_down(s0, 16),
+                         s17 = __shfl_down(s0, 17);
+            const int s = (16 * a + q + 4 * t) >> 1;
+            if (!(q & 1) && !(m & 1) && s < r && j < nc)
+              bpart[(((size_t)b * nchunk + c) * r + s) * n2 + j0 + j] = make_double2(s0 + s17, s1 - s16);
           }
         }
       }

@@ -212,7 +212,7 @@ void ystep_split(int n2, int r, int nb, int* ny, int* cw) {
 #define YS_CP1 12   // chunk partials of X~^* W~ in the first batch of loads
 #define YS_CP 8     // and in each later batch
 template <int RM>
-__global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const float2* __restrict__ bpart,
+__global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const double2* __restrict__ bpart,
                                                const cd* __restrict__ gxp, const cd* __restrict__ qx,
                                                const int* __restrict__ qx_zero, cd* __restrict__ gyq, int n2,
                                                int r, int n3, int nchunk, int cw, int ny, double eta, int init) {
@@ -238,7 +238,9 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const fl
     g4[k] = ld_or(gxp, (size_t)b * rr + e, !init && e < rr, zc);
     q4[k] = ld_or(qx, (size_t)b * rr + e, !qzero && e < rr, zc);
   }
-  float2 y[2], v[2][YS_CP1];
+  const double2 zd = make_double2(0.0, 0.0);
+  float2 y[2];
+  double2 v[2][YS_CP1];
   size_t base[2];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -247,7 +249,7 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const fl
     y[u] = ld_or(yt, ((size_t)b * r + t) * n2 + j0 + jj, e < nel, z2);
 #pragma unroll
     for (int k = 0; k < YS_CP1; ++k)
-      v[u][k] = ld_or(bpart, base[u] + (size_t)k * r * n2, !init && e < nel && k < nchunk, z2);
+      v[u][k] = ld_or(bpart, base[u] + (size_t)k * r * n2, !init && e < nel && k < nchunk, zd);
   }
   cd acc[2];
 #pragma unroll
@@ -261,12 +263,12 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const fl
   }
   if (!init) {
     for (int c0 = YS_CP1; c0 < nchunk; c0 += YS_CP) {
-      float2 w[2][YS_CP];
+      double2 w[2][YS_CP];
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int k = 0; k < YS_CP; ++k)
-          w[u][k] = ld_or(bpart, base[u] + (size_t)(c0 + k) * r * n2, tid + 256 * u < nel && c0 + k < nchunk, z2);
+          w[u][k] = ld_or(bpart, base[u] + (size_t)(c0 + k) * r * n2, tid + 256 * u < nel && c0 + k < nchunk, zd);
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll

@@ -135,74 +135,12 @@ __device__ inline int pinv_gj_wave16(const cd* A, cd* P, int r) {
   return 1;
 }
 
-// Returns 1 (to every thread) if all eigenvalues were kept, 0 otherwise.
-__device__ inline int pinv_herm(const cd* A, cd* P, int r, int force_eigen, PinvScratch s) {
+// Cyclic Jacobi eigen-decomposition of a Hermitian r x r matrix A by the whole block, with
+// parallel (round-robin) pair ordering: on return s.work holds the rotated matrix (the
+// eigenvalues on its diagonal, unsorted) and s.vec the eigenvectors as columns.  fro is
+// ||A||_F (the sweeps stop when the off-diagonal part falls below 1e-14 fro).
+__device__ inline void jacobi_herm(const cd* A, int r, double fro, PinvScratch s) {
   const int tid = threadIdx.x, nt = blockDim.x, rr = r * r;
-  if (!force_eigen && r <= 16) {
-    if (tid < 64) {
-      const int f = pinv_gj_wave16(A, P, r);
-      if (tid == 0) s.rot[0] = (double)f;
-    }
-    __syncthreads();
-    const int f = (int)s.rot[0];
-    __syncthreads();
-    if (f == 1) return 1;
-    if (f == 2 || f == 3) return 0;
-  }
-  double f2 = 0.0, dmax = -1.0;
-  for (int e = tid; e < rr; e += nt) {
-    cd a = A[e];
-    f2 += a.re * a.re + a.im * a.im;
-    if (e / r == e % r) dmax = fmax(dmax, a.re);
-  }
-  f2 = block_sum_d(f2, s.red);
-  dmax = block_max_d(dmax, s.red);
-  if (!isfinite(f2)) {
-    for (int e = tid; e < rr; e += nt) P[e] = cd_make(NAN, NAN);
-    __syncthreads();
-    return 0;
-  }
-  if (!(dmax > 0.0)) {   // PSD with a non-positive diagonal: the zero matrix
-    for (int e = tid; e < rr; e += nt) P[e] = cd_make(0.0, 0.0);
-    __syncthreads();
-    return 0;
-  }
-  const double fro = sqrt(f2);
-
-  if (!force_eigen && r > 16) {   // block-level Gauss-Jordan for the larger ranks
-    for (int e = tid; e < rr; e += nt) s.work[e] = A[e];
-    __syncthreads();
-    bool ok = true;
-    for (int k = 0; k < r; ++k) {
-      const double piv = s.work[k * r + k].re;
-      if (!(piv > 0.0)) { ok = false; break; }            // uniform across the block
-      for (int e = tid; e < r; e += nt) { s.colk[e] = s.work[e * r + k]; s.rowk[e] = s.work[k * r + e]; }
-      __syncthreads();
-      const double ip = 1.0 / piv;
-      for (int e = tid; e < rr; e += nt) {
-        const int p = e / r, q = e % r;
-        cd v;
-        if (p == k && q == k) v = cd_make(-ip, 0.0);
-        else if (p == k) v = cd_scale(s.rowk[q], ip);
-        else if (q == k) v = cd_scale(s.colk[p], ip);
-        else v = cd_sub(s.work[e], cd_scale(cd_mul(s.colk[p], s.rowk[q]), ip));
-        s.work[e] = v;
-      }
-      __syncthreads();
-    }
-    if (ok) {
-      double g2 = 0.0;
-      for (int e = tid; e < rr; e += nt) g2 += s.work[e].re * s.work[e].re + s.work[e].im * s.work[e].im;
-      g2 = block_sum_d(g2, s.red);
-      if (isfinite(g2) && 8.0 * r * TCTF_EPS64 * fro * sqrt(g2) < 1.0) {
-        for (int e = tid; e < rr; e += nt) P[e] = cd_make(-s.work[e].re, -s.work[e].im);
-        __syncthreads();
-        return 1;
-      }
-    }
-  }
-
-  // Jacobi eigen-decomposition of A into work (eigenvalues on the diagonal) and vec.
   for (int e = tid; e < rr; e += nt) {
     s.work[e] = A[e];
     s.vec[e] = cd_make((e / r == e % r) ? 1.0 : 0.0, 0.0);
@@ -271,6 +209,77 @@ __device__ inline int pinv_herm(const cd* A, cd* P, int r, int force_eigen, Pinv
       __syncthreads();
     }
   }
+}
+
+// Returns 1 (to every thread) if all eigenvalues were kept, 0 otherwise.
+__device__ inline int pinv_herm(const cd* A, cd* P, int r, int force_eigen, PinvScratch s) {
+  const int tid = threadIdx.x, nt = blockDim.x, rr = r * r;
+  if (!force_eigen && r <= 16) {
+    if (tid < 64) {
+      const int f = pinv_gj_wave16(A, P, r);
+      if (tid == 0) s.rot[0] = (double)f;
+    }
+    __syncthreads();
+    const int f = (int)s.rot[0];
+    __syncthreads();
+    if (f == 1) return 1;
+    if (f == 2 || f == 3) return 0;
+  }
+  double f2 = 0.0, dmax = -1.0;
+  for (int e = tid; e < rr; e += nt) {
+    cd a = A[e];
+    f2 += a.re * a.re + a.im * a.im;
+    if (e / r == e % r) dmax = fmax(dmax, a.re);
+  }
+  f2 = block_sum_d(f2, s.red);
+  dmax = block_max_d(dmax, s.red);
+  if (!isfinite(f2)) {
+    for (int e = tid; e < rr; e += nt) P[e] = cd_make(NAN, NAN);
+    __syncthreads();
+    return 0;
+  }
+  if (!(dmax > 0.0)) {   // PSD with a non-positive diagonal: the zero matrix
+    for (int e = tid; e < rr; e += nt) P[e] = cd_make(0.0, 0.0);
+    __syncthreads();
+    return 0;
+  }
+  const double fro = sqrt(f2);
+
+  if (!force_eigen && r > 16) {   // block-level Gauss-Jordan for the larger ranks
+    for (int e = tid; e < rr; e += nt) s.work[e] = A[e];
+    __syncthreads();
+    bool ok = true;
+    for (int k = 0; k < r; ++k) {
+      const double piv = s.work[k * r + k].re;
+      if (!(piv > 0.0)) { ok = false; break; }            // uniform across the block
+      for (int e = tid; e < r; e += nt) { s.colk[e] = s.work[e * r + k]; s.rowk[e] = s.work[k * r + e]; }
+      __syncthreads();
+      const double ip = 1.0 / piv;
+      for (int e = tid; e < rr; e += nt) {
+        const int p = e / r, q = e % r;
+        cd v;
+        if (p == k && q == k) v = cd_make(-ip, 0.0);
+        else if (p == k) v = cd_scale(s.rowk[q], ip);
+        else if (q == k) v = cd_scale(s.colk[p], ip);
+        else v = cd_sub(s.work[e], cd_scale(cd_mul(s.colk[p], s.rowk[q]), ip));
+        s.work[e] = v;
+      }
+      __syncthreads();
+    }
+    if (ok) {
+      double g2 = 0.0;
+      for (int e = tid; e < rr; e += nt) g2 += s.work[e].re * s.work[e].re + s.work[e].im * s.work[e].im;
+      g2 = block_sum_d(g2, s.red);
+      if (isfinite(g2) && 8.0 * r * TCTF_EPS64 * fro * sqrt(g2) < 1.0) {
+        for (int e = tid; e < rr; e += nt) P[e] = cd_make(-s.work[e].re, -s.work[e].im);
+        __syncthreads();
+        return 1;
+      }
+    }
+  }
+
+  // Jacobi eigen-decomposition of A into work (eigenvalues on the diagonal) and vec.
+  jacobi_herm(A, r, fro, s);
   double lmax = -1e300;
   for (int i = tid; i < r; i += nt) lmax = fmax(lmax, s.work[i * r + i].re);
   lmax = block_max_d(lmax, s.red);

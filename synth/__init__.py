@@ -3,6 +3,6 @@
 This package only draws input data (observed tensor, sampling mask, initial factors).
 It holds none of the completion method's arithmetic; see ``synth.traffic``.
 """
-from .traffic import WORKLOADS, Workload, batch_specs, make_inputs, make_workload
+from .traffic import LAYOUTS, WORKLOADS, Workload, batch_specs, make_inputs, make_workload, relayout
 
-__all__ = ["WORKLOADS", "Workload", "batch_specs", "make_inputs", "make_workload"]
+__all__ = ["LAYOUTS", "WORKLOADS", "Workload", "batch_specs", "make_inputs", "make_workload", "relayout"]

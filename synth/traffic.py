@@ -156,3 +156,40 @@ def batch_specs(count: int = 64, seed: int = 1) -> list[Workload]:
         out.append(Workload(f"batch{t}_{n1}x{n2}x{n3}_r{r}", n1, n2, n3, r, 1.0, True, 0.02, p, 50,
                             seed=1000 + t))
     return out
+
+
+LAYOUTS = {
+    # the generator's layout: OD pair x time slot x day (mode 3, the tube, is the day)
+    "od_slot_day": "OD pair x slot x day",
+    # the paper's model layout t x d x o (section 3.1): slot x day x OD pair
+    "slot_day_od": "slot x day x OD pair",
+    # the router-pair layout of the paper's experiments (N x N x T): origin x destination x
+    # time, with time running over the days' slots in order (T = slots x days)
+    "origin_destination_time": "origin x destination x time",
+}
+
+
+def relayout(d: dict, layout: str, r: int, seed: int) -> dict:
+    """The same observations in another layout: M, G and the masks permuted (or reshaped),
+    and a new start X0 = 0, Y0 ~ N(0, 1) of the new shape from default_rng(seed + 1).  Input
+    arrays are (o, t, d) = (OD pair, slot, day); the origin-destination form needs o = N^2."""
+    def move(a):
+        if a is None:
+            return None
+        if layout == "od_slot_day":
+            return a
+        if layout == "slot_day_od":
+            return np.ascontiguousarray(np.transpose(a, (1, 2, 0)))
+        if layout == "origin_destination_time":
+            o, t, dd = a.shape
+            n = int(round(np.sqrt(o)))
+            if n * n != o:
+                raise ValueError("the origin x destination layout needs a square number of OD pairs")
+            return np.ascontiguousarray(np.transpose(a, (0, 2, 1)).reshape(n, n, dd * t))
+        raise KeyError(layout)
+    out = {k: move(d[k]) for k in ("M", "G", "omega", "holdout")}
+    n1, n2, n3 = out["M"].shape
+    rng0 = np.random.default_rng(seed + 1)
+    out["Y0"] = np.ascontiguousarray(rng0.normal(0.0, 1.0, size=(r, n2, n3)), dtype=np.float32)
+    out["X0"] = np.zeros((n1, r, n3), dtype=np.float32)
+    return out

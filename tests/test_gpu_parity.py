@@ -281,3 +281,34 @@ def test_three_launch_slice_path_mixed_precision():
     c = gpu_run(d, 3, 30, precision="mixed")
     assert np.array_equal(b["W"], c["W"])
     assert rel(b["W"], a["W"]) < 1e-2
+
+
+@pytest.mark.parametrize("layout,iters", [("slot_day_od", 20), ("origin_destination_time", 6)])
+def test_paper_layouts_of_the_144x288x28_workload(layout, iters):
+    """The 40 %-sampled 144 x 288 x 28 data in the paper's slot x day x OD layout (288 x 28 x
+    144, section 3.1) and in the router-pair layout (12 x 12 x 8064, section 5) against the
+    oracle on the same layout."""
+    from synth import relayout
+    w, d = make_workload("od144x288x28_r8_p40")
+    e = relayout(d, layout, w.r, w.seed)
+    g = gpu_run(e, w.r, iters)
+    st, info = oracle_run(e, w.r, iters)
+    info["f0"] = [oracle.objective(info["problem"], st)]
+    _compare(g, st, info, label=f"{layout} {tuple(e['M'].shape)} ({iters} it)")
+
+
+@pytest.mark.parametrize("tol,every", [(0.05, 5), (0.2, 3)])
+def test_rank_adjustment_against_the_oracle(tol, every):
+    """Step 5 every `every` iterations with threshold tol (singular values of Z~_k against tol
+    times the largest): the rank vector equals the oracle's (FP64 SVD of every frequency's
+    n1 x n2 product) and W, Z stay on the oracle's trajectory over 12 iterations.  The
+    thresholds sit at least 2 % away from every singular value of this run."""
+    n1, n2, n3, r = 40, 36, 12, 5
+    d = make_inputs(n1, n2, n3, r, p=0.5, seed=55, weekly=True)
+    g = gpu_run(d, r, 12, rank_tol=tol, rank_every=every)
+    st, info = oracle.complete(d["G"], d["omega"], r, d["X0"], d["Y0"], 12, rank_tol=tol, rank_every=every)
+    ranks = g["ctx"].rank_vector()
+    print(f"tol {tol} every {every}: ranks {ranks} (oracle {list(info['ranks'][:n3 // 2 + 1])})", flush=True)
+    assert ranks == [int(v) for v in info["ranks"][:n3 // 2 + 1]]
+    assert min(ranks) < r
+    _compare(g, st, None, label=f"rank adjustment tol {tol} every {every}")

@@ -290,3 +290,69 @@ def test_metrics():
     om = np.array([[[1, 1], [1, 0]]], dtype=np.uint8)
     assert np.isclose(O.nmae(w, m, om), 1.0 / 4.0)
     assert np.isclose(O.rse(w, m), 1.0 / np.sqrt(30.0))
+
+
+# ----------------------------------------------------------------------------- step 5
+
+def _iterated_state(seed=8, shape=(9, 8, 6), r=4, iters=3, **kw):
+    d = make_inputs(*shape, r, p=0.6, seed=seed, weekly=True)
+    prob = O.Problem(d["G"], d["omega"], r, **kw)
+    st = O.initial_state(prob, d["X0"], d["Y0"])
+    for _ in range(iters):
+        st = O.iterate(prob, st)
+    return prob, st
+
+
+def test_rank_adjust_without_threshold_keeps_the_product():
+    prob, st = _iterated_state()
+    adj, ranks = O.rank_adjust(prob, st, 0.0)
+    np.testing.assert_allclose(O.z_of(adj), O.z_of(st), atol=1e-10 * np.abs(O.z_of(st)).max())
+    assert np.all(ranks == prob.r)
+
+
+@pytest.mark.parametrize("tol", [0.05, 0.2])
+def test_rank_adjust_is_the_best_approximation_of_each_frequency(tol):
+    """Eckart-Young: the kept part of Z~_k has rank r_k and misses Z~_k by exactly the
+    dropped singular values; the dropped ones are those below tol * (largest overall); the
+    adjusted factors keep the conjugate symmetry eq. (rcm_3-k+2)."""
+    prob, st = _iterated_state()
+    adj, ranks = O.rank_adjust(prob, st, tol)
+    m3 = prob.shape[2]
+    zt = np.einsum("irk,rjk->ijk", st.xt, st.yt)
+    za = np.einsum("irk,rjk->ijk", adj.xt, adj.yt)
+    sv = [np.linalg.svd(zt[:, :, k], compute_uv=False) for k in range(m3)]
+    smax = max(s[0] for s in sv)
+    assert ranks.min() < prob.r   # the threshold bites somewhere at these settings
+    for k in range(m3):
+        q = ranks[k]
+        assert q == int(np.sum(sv[k][:prob.r] > tol * smax))
+        assert np.linalg.matrix_rank(za[:, :, k], tol=1e-9 * smax) == q
+        err = np.linalg.norm(zt[:, :, k] - za[:, :, k]) ** 2
+        assert np.isclose(err, np.sum(sv[k][q:] ** 2), rtol=1e-8, atol=1e-18 * smax ** 2)
+        assert np.all(adj.xt[:, q:, k] == 0) and np.all(adj.yt[q:, :, k] == 0)
+    for k in range(1, m3):
+        np.testing.assert_allclose(adj.xt[:, :, k], np.conj(adj.xt[:, :, m3 - k]), atol=1e-12)
+
+
+def test_rank_adjust_recovers_the_exact_tubal_rank():
+    """A fully observed tensor of exact tubal rank 2 fitted with r = 4 (rho1 = 0: Z = G after one
+    sweep): step 5 with a small threshold leaves rank 2 in every frequency and the same Z."""
+    rng = np.random.default_rng(12)
+    g = O.tprod(rng.normal(size=(10, 2, 5)), rng.normal(size=(2, 9, 5)))
+    om = np.ones(g.shape, dtype=np.uint8)
+    st, info = O.complete(g, om, 4, np.zeros((10, 4, 5)), rng.normal(size=(4, 9, 5)), 1, mu=0.1, rho1=0.0,
+                          rho2=0.3, rank_tol=1e-8, rank_every=1)
+    assert np.all(info["ranks"] == 2)
+    assert O.tubal_rank(O.z_of(st)) == 2
+    np.testing.assert_allclose(O.z_of(st), g, atol=1e-10 * np.abs(g).max())
+
+
+def test_dropped_components_stay_zero_in_later_iterations():
+    """After step 5 the pseudo-inverse steps of eq. (updataXYW1) never bring a dropped
+    component back (its Gram rows are zero, so Lemma SVPMPI's inverse leaves it out)."""
+    prob, st = _iterated_state()
+    adj, ranks = O.rank_adjust(prob, st, 0.2)
+    nxt = O.iterate(prob, adj)
+    for k in range(prob.shape[2]):
+        assert np.abs(nxt.xt[:, ranks[k]:, k]).max() == 0.0
+        assert np.abs(nxt.yt[ranks[k]:, :, k]).max() == 0.0
