@@ -139,10 +139,12 @@ def measured_traffic(stage, prec):
         return None
 
 
-def batch_bench(count, steps, warmup):
+def batch_bench(count, steps, warmup, autotune=False):
     """Aggregate iterations/s of `count` uneven completions: sequential single-completion
     runs (each with its own graph replays) against one batch (one graph launch per block of
-    iterations, members as independent branches)."""
+    iterations, members as independent branches).  With autotune every member (and every
+    single completion) takes its tuned execution shape; tuning happens at create, outside
+    the timed regions."""
     import numpy as np
     import torch
     from paper_2005_09838_amd import Batch, Completion
@@ -154,9 +156,14 @@ def batch_bench(count, steps, warmup):
         d = make_inputs(w.n1, w.n2, w.n3, w.r, sigma_od=w.sigma_od, weekly=w.weekly, noise=w.noise, p=w.p,
                         seed=w.seed)
         probs.append({"G": torch.from_numpy(d["G"]).to(dev), "omega": torch.from_numpy(d["omega"]).to(dev),
-                      "r": w.r, "X0": torch.from_numpy(d["X0"]).to(dev), "Y0": torch.from_numpy(d["Y0"]).to(dev)})
+                      "r": w.r, "X0": torch.from_numpy(d["X0"]).to(dev), "Y0": torch.from_numpy(d["Y0"]).to(dev),
+                      "autotune": autotune})
         nbytes += algorithmic_bytes(w.n1, w.n2, w.n3, w.r, False)
-    singles = [Completion(pr["G"], pr["omega"], pr["r"], X0=pr["X0"], Y0=pr["Y0"]) for pr in probs]
+    t_tune = time.perf_counter()
+    singles = [Completion(pr["G"], pr["omega"], pr["r"], X0=pr["X0"], Y0=pr["Y0"], autotune=autotune)
+               for pr in probs]
+    t_tune = time.perf_counter() - t_tune
+    tunings = [c.tuning() for c in singles]
     for c in singles:
         c.step(warmup)
     torch.cuda.synchronize()
@@ -189,6 +196,9 @@ def batch_bench(count, steps, warmup):
         "hbm_gbps_algorithmic_batch": round(nbytes * steps / t_batch / 1e9, 1),
         "hbm_gbps_algorithmic_sequential": round(nbytes * steps / t_seq / 1e9, 1),
         "batch_results_equal_single_runs": same,
+        "autotune": autotune,
+        "create_seconds_sequential_contexts": round(t_tune, 3),
+        "slice_paths": {str(k): sum(1 for t in tunings if t[0] == k) for k in (1, 2, 3)},
     }
     print(json.dumps(line), flush=True)
 
@@ -332,6 +342,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB")
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT")
     ap.add_argument("--layouts", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="with --batch: tuned execution shapes")
     ap.add_argument("--only", choices=("fp32", "mixed"), default=None,
                     help="run one precision (no equal-error comparison); for counter runs")
     args = ap.parse_args()
@@ -343,7 +354,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.batch:
-        batch_bench(args.batch, args.steps, args.warmup)
+        batch_bench(args.batch, args.steps, args.warmup, args.autotune)
         return
     if args.layouts:
         layout_bench(args.rse_iters, (10, 20, 40, 60, 80))

@@ -84,7 +84,14 @@ typedef struct {
                            0 (default) = never, the rank vector stays r everywhere.  With
                            rank_every > 0 iterations are launched eagerly (no graph replay)
                            and batches refuse the context                                   */
-  int32_t reserved;     /* 0 */
+  int32_t autotune;     /* 1: tctf_create times the execution shapes this problem allows (the
+                           fusion depth of steps 3, 4 and 7: one fused kernel per OD row with
+                           several or one thread per tube, or three launches; rows per
+                           X~^* W~ chunk; columns per Y-step block) and keeps the fastest,
+                           remembered per shape and device for the process (later contexts
+                           of the shape reuse it); the workspace is sized for every shape.
+                           Shapes change summation orders only.  0 (default): fixed rules.
+                           tctf_complete_noalloc ignores it                                  */
 } tctf_params;
 /* Sizes: n1 <= 8192, n2 <= 1024, n3 <= 8192.  For n3 in 1..16, 20, 24, 28, 32, 40, 48, 56,
  * 64, 84, 96, 112, 128 (the lengths the tube transform is generated for) with one slice
@@ -176,6 +183,11 @@ tctf_status tctf_set_state(tctf_ctx* c, const void* src, size_t bytes);
  * from the r x r Grams in FP64, and zeroes the dropped components; f0's fit, ridge and K
  * terms after an adjusting iteration are those of its W-step (taken before the truncation). */
 tctf_status tctf_rank_vector(tctf_ctx* c, int32_t* ranks);
+
+/* The execution shape in use: out[0] = slice path (1 fused, several threads per tube;
+ * 2 fused, one thread per tube; 3 three launches), out[1] = rows per X~^* W~ chunk,
+ * out[2] = columns per Y-step block, out[3] = 1 if it came from the process's tuning cache. */
+tctf_status tctf_tuning(tctf_ctx* c, int32_t out[4]);
 
 /* Iterations run since create (or as restored). */
 tctf_status tctf_iterations(tctf_ctx* c, int64_t* iters);

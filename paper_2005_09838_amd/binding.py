@@ -24,7 +24,7 @@ class tctf_params(ctypes.Structure):
                 ("mu", ctypes.c_double), ("rho1", ctypes.c_double), ("rho2", ctypes.c_double),
                 ("eta", ctypes.c_double), ("precision", ctypes.c_int32), ("pinv_mode", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("rank_tol", ctypes.c_double), ("rank_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32)]
 
 
 class TctfError(RuntimeError):
@@ -61,6 +61,7 @@ def library() -> ctypes.CDLL:
         "tctf_set_state": (I32, [P, P, S]),
         "tctf_iterations": (I32, [P, ctypes.POINTER(I64)]),
         "tctf_rank_vector": (I32, [P, ctypes.POINTER(I32)]),
+        "tctf_tuning": (I32, [P, ctypes.POINTER(I32)]),
         "tctf_destroy": (None, [P]),
         "tctf_complete": (I32, [PP, P, P, P, P, U64, I32, P, S, P, P, ctypes.POINTER(D)]),
         "tctf_time_stage": (I32, [P, I32, I32, ctypes.POINTER(D)]),
@@ -175,6 +176,12 @@ def tctf_rank_vector(ctx, nb: int) -> list:
     return list(v)
 
 
+def tctf_tuning(ctx) -> tuple:
+    v = (ctypes.c_int32 * 4)()
+    _check(library().tctf_tuning(ctx, v), "tctf_tuning")
+    return tuple(v)
+
+
 def tctf_iterations(ctx) -> int:
     v = ctypes.c_int64()
     _check(library().tctf_iterations(ctx, ctypes.byref(v)), "tctf_iterations")
@@ -260,7 +267,7 @@ def tctf_last_error() -> str:
 # ---------------------------------------------------------------- torch convenience layer
 
 def make_params(n1, n2, n3, r, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision="fp32", pinv_mode=0,
-                eps=1e-6, rank_tol=0.0, rank_every=0) -> tctf_params:
+                eps=1e-6, rank_tol=0.0, rank_every=0, autotune=False) -> tctf_params:
     p = tctf_default_params()
     p.n1, p.n2, p.n3, p.r = int(n1), int(n2), int(n3), int(r)
     p.mu, p.rho1, p.rho2, p.eta = float(mu), float(rho1), float(rho2), float(eta)
@@ -270,6 +277,7 @@ def make_params(n1, n2, n3, r, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision
     p.eps = float(eps)
     p.rank_tol = float(rank_tol)
     p.rank_every = int(rank_every)
+    p.autotune = 1 if autotune else 0
     return p
 
 
@@ -297,7 +305,8 @@ class Completion:
         return self
 
     def __init__(self, G, omega, r, *, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision="fp32",
-                 pinv_mode=0, eps=1e-6, X0=None, Y0=None, seed=0, stream=None, rank_tol=0.0, rank_every=0):
+                 pinv_mode=0, eps=1e-6, X0=None, Y0=None, seed=0, stream=None, rank_tol=0.0, rank_every=0,
+                 autotune=False):
         import torch
         self._owned = True
         if not (G.is_cuda and omega.is_cuda):
@@ -309,7 +318,7 @@ class Completion:
         self.X0 = None if X0 is None else X0.contiguous().to(torch.float32)
         self.Y0 = None if Y0 is None else Y0.contiguous().to(torch.float32)
         self.params = make_params(n1, n2, n3, r, mu, rho1, rho2, eta, precision, pinv_mode, eps, rank_tol,
-                                  rank_every)
+                                  rank_every, autotune)
         self.shape = (n1, n2, n3)
         self.r = r
         self.stream = stream
@@ -356,6 +365,10 @@ class Completion:
 
     def stationarity(self):
         return tctf_stationarity(self.ctx)
+
+    def tuning(self):
+        """(slice path, rows per X~^* W~ chunk, columns per Y-step block, from the cache)."""
+        return tctf_tuning(self.ctx)
 
     def rank_vector(self):
         """Step 5's rank vector r_b of the stored frequencies b = 0 .. n3 / 2."""
@@ -445,7 +458,8 @@ class Batch:
             om = pr["omega"].contiguous().to(torch.uint8)
             n1, n2, n3 = G.shape
             self.params[k] = make_params(n1, n2, n3, pr["r"], pr.get("mu", 1e-2), pr.get("rho1", 1e-2),
-                                         pr.get("rho2", 1e-2), pr.get("eta", 1.0), pr.get("precision", "fp32"))
+                                         pr.get("rho2", 1e-2), pr.get("eta", 1.0), pr.get("precision", "fp32"),
+                                         autotune=pr.get("autotune", False))
             ptrs["G"][k], ptrs["omega"][k] = G.data_ptr(), om.data_ptr()
             keep += [G, om]
             for key in ("X0", "Y0"):

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <array>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -50,9 +52,10 @@ struct StateHeader {
 };
 
 struct Layout {
-  size_t gp, wt, zt, xt, yt, rhs, bpart, gxm, dmat, gxp, qx, qx_zero, gym, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
+  size_t gp, wt, zt, xt, yt, rhs, bpart, gxpart, gxm, dmat, gxp, qx, qx_zero, gym, gyp, qy, qy_zero, slice_obj, bin_obj, wtab, htab,
       flag, ctr, zsp, wsp, csp, twg, rsig, rtx, rty, ranks, scal, xt_prev, yt_prev, wt_prev, stat_work, kkt, total;
   size_t state_bytes;
+  bool split;   // the three-launch slice path's buffers exist
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -72,12 +75,32 @@ static void chunking(int n1, int nb, int* nchunk, int* chunk) {
   *chunk = ch;
 }
 
+// Tunable execution shape of one context: the slice path (tctf::SlicePath, the fusion
+// depth of steps 3, 4 and 7), the rows per X~^* W~ chunk and the columns per Y-step block.
+struct Knobs {
+  int spath, chunk, ycw;
+};
+#define TUNE_MIN_CHUNK 16
+#define TUNE_MIN_YCW 8
+
+static Knobs default_knobs(const tctf_params& p) {
+  Knobs k;
+  int nchunk, ny;
+  const int nb = p.n3 / 2 + 1;
+  k.spath = tctf::slice_default_path(p.n2, p.n3);
+  chunking(p.n1, nb, &nchunk, &k.chunk);
+  tctf::ystep_split(p.n2, p.r, nb, &ny, &k.ycw);
+  return k;
+}
+
 static Layout make_layout(const tctf_params& p) {
   Layout L;
   const size_t n1 = p.n1, n2 = p.n2, n3 = p.n3, r = p.r, nb = n3 / 2 + 1;
-  int nchunk, chunk, ny, ycw;
-  chunking(p.n1, (int)nb, &nchunk, &chunk);
-  tctf::ystep_split(p.n2, p.r, (int)nb, &ny, &ycw);
+  // buffers sized for the default shape, or for every shape the autotuner may pick
+  const Knobs dk = default_knobs(p);
+  const int chunk = p.autotune ? TUNE_MIN_CHUNK : dk.chunk;
+  const int ycw = p.autotune ? (TUNE_MIN_YCW < p.n2 ? TUNE_MIN_YCW : p.n2) : dk.ycw;
+  const size_t nchunk = (n1 + chunk - 1) / chunk, ny = (n2 + ycw - 1) / ycw;
   const size_t welem = p.precision == TCTF_MIXED_BF16 ? 4 : 8;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
@@ -88,6 +111,7 @@ static Layout make_layout(const tctf_params& p) {
   L.yt = take(nb * r * n2 * 8);
   L.rhs = take(nb * r * n1 * 8);
   L.bpart = take(nb * nchunk * r * n2 * 16);
+  L.gxpart = take(nb * (size_t)tctf::gramx_groups(p.n1) * 2 * r * r * 16);
   L.gxm = take(nb * r * r * 16);
   L.dmat = take(nb * r * r * 16);
   L.gxp = take(nb * r * r * 16);
@@ -103,11 +127,12 @@ static Layout make_layout(const tctf_params& p) {
   L.htab = take(3 * n1 * 4);
   L.flag = take(64);
   L.ctr = take(64);
-  const bool gen = !tctf::slice_fused(p.n2, p.n3);   // the three-launch slice path
+  const bool gen = p.autotune || dk.spath == tctf::SPATH_SPLIT;   // the three-launch slice path
   L.zsp = take(gen ? n1 * n2 * n3 * 4 : 0);
   L.wsp = take(gen ? n1 * n2 * n3 * 4 : 0);
   L.csp = take(gen ? n1 * n2 * n3 * 4 : 0);
   L.twg = take(gen ? n3 * 16 : 0);
+  L.split = gen;
   L.rsig = take(nb * r * 8);
   L.rtx = take(nb * r * r * 16);
   L.rty = take(nb * r * r * 16);
@@ -133,6 +158,8 @@ struct tctf_ctx {
   int device;
   int64_t iters;
   bool term_valid;
+  Knobs knobs;
+  int tuned_from_cache = 0;
   bool track = false;   // step 6 evaluated after every tctf_step call (tctf_track_termination)
   bool eager = false;   // never capture or replay a graph (the allocation-free entry point)
   // stage timing of tctf_step (tctf_profile): one event pair per profiled launch
@@ -145,6 +172,10 @@ struct tctf_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // inside the captured graph, G_X and its inverse run on a branch beside the X~^* W~ products
+  hipStream_t br_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool capturing = false;
 };
 
 #define GRAPH_ITERS 10
@@ -165,6 +196,7 @@ static tctf_status validate(const tctf_params* p) {
   if (p->pinv_mode != 0 && p->pinv_mode != 1) return fail(TCTF_E_ARG, "pinv_mode must be 0 or 1");
   if (!(p->eps >= 0.0)) return fail(TCTF_E_ARG, "eps must be >= 0");
   if (!(std::isfinite(p->rank_tol) && p->rank_tol >= 0.0)) return fail(TCTF_E_ARG, "rank_tol must be finite and >= 0");
+  if (p->autotune != 0 && p->autotune != 1) return fail(TCTF_E_ARG, "autotune must be 0 or 1");
   if (p->rank_every < 0) return fail(TCTF_E_ARG, "rank_every must be >= 0");
   return TCTF_OK;
 }
@@ -201,8 +233,11 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.n3 = p.n3;
   q.r = p.r;
   q.nb = p.n3 / 2 + 1;
-  chunking(p.n1, q.nb, &q.nchunk, &q.chunk);
-  tctf::ystep_split(p.n2, p.r, q.nb, &q.ny, &q.ycw);
+  q.spath = c->knobs.spath;
+  q.chunk = c->knobs.chunk;
+  q.nchunk = (p.n1 + q.chunk - 1) / q.chunk;
+  q.ycw = c->knobs.ycw;
+  q.ny = (p.n2 + q.ycw - 1) / q.ycw;
   q.mu = p.mu;
   q.rho1 = p.rho1;
   q.rho2 = p.rho2;
@@ -217,6 +252,7 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.yt = (float2*)(w + L.yt);
   q.rhs = (float2*)(w + L.rhs);
   q.bpart = (double2*)(w + L.bpart);
+  q.gxpart = (cd*)(w + L.gxpart);
   q.gxm = (cd*)(w + L.gxm);
   q.dmat = (cd*)(w + L.dmat);
   q.gxp = (cd*)(w + L.gxp);
@@ -280,11 +316,30 @@ static tctf_status enqueue_iteration(tctf_ctx* c) {
   tctf_status s = TCTF_OK;
   if (s == TCTF_OK) s = stage(c, 2, [&] { tctf::launch_agemm(p, 0, 1); });
   if (s == TCTF_OK) s = stage(c, 3, [&] { tctf::launch_hsolve(p); });
-  if (s == TCTF_OK) s = stage(c, 4, [&] { tctf::launch_bgemm(p); });
+  if (s == TCTF_OK && c->capturing) {
+    // G_X, its pseudo-inverse and I - eta P_X are needed first by the Y-step: in the graph they
+    // form a branch that runs beside the X~^* W~ chunk products and joins before the Y-step
+    hipError_t e = hipEventRecord(c->ev_fork, p.stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->br_stream, c->ev_fork, 0);
+    if (e == hipSuccess) {
+      Plan pb = p;
+      pb.stream = c->br_stream;
+      tctf::launch_gramx(pb);
+      e = hipEventRecord(c->ev_join, c->br_stream);
+    }
+    tctf::launch_bgemm(p);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p.stream, c->ev_join, 0);
+    if (e != hipSuccess) s = fail(TCTF_E_HIP, "branch of the G_X launches: %s", hipGetErrorString(e));
+  } else if (s == TCTF_OK) {
+    s = stage(c, 4, [&] {
+      tctf::launch_gramx(p);
+      tctf::launch_bgemm(p);
+    });
+  }
   if (s == TCTF_OK) s = stage(c, 5, [&] { tctf::launch_ystep(p, 0); });
   // Z~ = X~Y~; G_Y^+ and I - eta P_Y for the next X-step ride along in extra blocks of the
   // cooperative slice launch, or of this launch where the slice runs the per-thread kernel
-  if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p, tctf::slice_hosts_pinvy(p.n2, p.n3) ? 0 : 1); });
+  if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p, tctf::slice_hosts_pinvy(p) ? 0 : 1); });
   if (s == TCTF_OK) s = stage(c, 0, [&] { tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0); });
   // step 5 after iterations rank_every, 2 rank_every, ... (c->iters counts the iterations
   // before this one; such contexts never replay graphs, so the count is exact)
@@ -299,7 +354,7 @@ static tctf_status enqueue_iteration(tctf_ctx* c) {
 // the first pseudo-inverses.  On failure the context holds nothing that needs releasing.
 static tctf_status ctx_init(tctf_ctx* c, const tctf_params* prm, const float* G, const uint8_t* omega,
                             const float* X0, const float* Y0, uint64_t seed, void* workspace, size_t ws_bytes,
-                            void* hip_stream) {
+                            void* hip_stream, const Knobs* knobs = nullptr) {
   tctf_status s = validate(prm);
   if (s != TCTF_OK) return s;
   if (!G || !omega) return fail(TCTF_E_ARG, "G and omega must be device pointers");
@@ -312,13 +367,15 @@ static tctf_status ctx_init(tctf_ctx* c, const tctf_params* prm, const float* G,
   c->ws = (unsigned char*)workspace;
   c->iters = 0;
   c->term_valid = false;
+  c->knobs = knobs ? *knobs : default_knobs(*prm);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) return fail(TCTF_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
   fill_plan(c, (hipStream_t)hip_stream);
   const Plan& p = c->plan;
-  tctf::slice_set_attr(p.n3, tctf::slice_launch_lds_bytes(p.n2, p.n3, p.r));
+  tctf::slice_set_attr(p.n3, tctf::slice_launch_lds_bytes(p));
   tctf::ystep_set_attr(tctf::ystep_lds_bytes(p.r, p.ycw));
   tctf::bgemm_set_attr(tctf::bgemm_lds_bytes(p.r, p.chunk));
+  tctf::gramx_set_attr(p.r);
   tctf::pinvy_set_attr(p.r);
   tctf::zgemm_set_attr(p.r);
   tctf::launch_zero(p, p.flag, 64);
@@ -328,7 +385,7 @@ static tctf_status ctx_init(tctf_ctx* c, const tctf_params* prm, const float* G,
   tctf::launch_zero(p, p.qy_zero, (size_t)p.nb * 4);
   tctf::launch_pack_g(p, G, omega);
   tctf::launch_tables(p);
-  if (!tctf::slice_fused(p.n2, p.n3)) tctf::launch_gen_twiddles(p);
+  if (c->lay.split) tctf::launch_gen_twiddles(p);   // the three-launch path's roots of unity
   if (X0) tctf::launch_tube_dft_setup(p, X0, p.xt, p.n1, p.r, (long)p.r * p.n1, 1, p.n1);
   else tctf::launch_zero(p, p.xt, (size_t)p.nb * p.r * p.n1 * 8);
   const float* y0 = Y0;
@@ -339,6 +396,7 @@ static tctf_status ctx_init(tctf_ctx* c, const tctf_params* prm, const float* G,
   tctf::launch_tube_dft_setup(p, y0, p.yt, p.r, p.n2, (long)p.r * p.n2, p.n2, 1);
   tctf::launch_zgemm(p);
   tctf::launch_slice(p, tctf::SLICE_INIT, nullptr, nullptr, 1);
+  tctf::launch_gramx(p);
   tctf::launch_bgemm(p);
   tctf::launch_ystep(p, 1);
   tctf::launch_pinvy(p, p.stream);
@@ -365,6 +423,101 @@ static void ctx_release(tctf_ctx* c) {
   c->graph = nullptr;
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   c->cap_stream = nullptr;
+  if (c->br_stream) hipStreamDestroy(c->br_stream);
+  c->br_stream = nullptr;
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
+  c->ev_fork = c->ev_join = nullptr;
+}
+
+static tctf_status enqueue_iteration(tctf_ctx* c);
+
+// ---- autotuning of the execution shape: the fusion depth of steps 3, 4 and 7 (the slice
+// path) and two tile shapes (rows per X~^* W~ chunk, columns per Y-step block), chosen per
+// problem shape by timing and kept for the process (per device).
+static std::mutex g_tune_mu;
+static std::map<std::array<int, 6>, Knobs> g_tune_cache;
+
+static std::array<int, 6> tune_key(const tctf_params& p, int device) {
+  return {p.n1, p.n2, p.n3, p.r, p.precision, device};
+}
+
+// Mean duration of one iteration over `reps` eager iterations after `warm`, from HIP events
+// on the context's stream.  The iterate advances (the caller rebuilds it).
+static tctf_status time_iterations(tctf_ctx* c, int warm, int reps, float* ms) {
+  const hipStream_t st = c->plan.stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  tctf_status s = TCTF_OK;
+  for (int k = 0; k < warm && s == TCTF_OK; ++k) s = enqueue_iteration(c);
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int k = 0; k < reps && s == TCTF_OK; ++k) s = enqueue_iteration(c);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (s != TCTF_OK) return s;
+  if (e != hipSuccess) return fail(TCTF_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+  *ms = t / reps;
+  return TCTF_OK;
+}
+
+// Coordinate search from the default shape: each slice path the sizes allow, then the chunk
+// rows, then the Y-step columns; every trial times a few iterations, after which the
+// initial iterate is built again.  The context ends at its initial iterate with the best
+// shape.
+static tctf_status autotune(tctf_ctx* c, const tctf_params* prm, const float* G, const uint8_t* omega,
+                            const float* X0, const float* Y0, uint64_t seed, void* ws, size_t ws_bytes,
+                            void* stream) {
+  const auto key = tune_key(*prm, c->device);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      const Knobs k = it->second;
+      c->tuned_from_cache = 1;
+      return ctx_init(c, prm, G, omega, X0, Y0, seed, ws, ws_bytes, stream, &k);
+    }
+  }
+  const int warm = 2, reps = 6;
+  Knobs best = c->knobs;
+  float tbest = 0.f;
+  tctf_status s = time_iterations(c, warm, reps, &tbest);
+  auto trial = [&](const Knobs& k) {
+    if (s != TCTF_OK) return;
+    s = ctx_init(c, prm, G, omega, X0, Y0, seed, ws, ws_bytes, stream, &k);
+    float t = 0.f;
+    if (s == TCTF_OK) s = time_iterations(c, warm, reps, &t);
+    if (s == TCTF_OK && t < tbest) {
+      tbest = t;
+      best = k;
+    }
+  };
+  for (int path : {tctf::SPATH_COOP, tctf::SPATH_THREAD, tctf::SPATH_SPLIT})
+    if (path != best.spath && tctf::slice_path_valid(path, prm->n2, prm->n3)) trial({path, best.chunk, best.ycw});
+  for (int chunk : {16, 32, 48, 64})
+    if (chunk != best.chunk && chunk >= TUNE_MIN_CHUNK) trial({best.spath, chunk, best.ycw});
+  const int ymax = 512 / prm->r < prm->n2 ? 512 / prm->r : prm->n2;   // the Y-step block holds r x ycw <= 512
+  for (int ycw : {8, 16, 32, 64, ymax})
+    if (ycw != best.ycw && ycw >= TUNE_MIN_YCW && ycw <= ymax) trial({best.spath, best.chunk, ycw});
+  if (s != TCTF_OK) return s;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  return ctx_init(c, prm, G, omega, X0, Y0, seed, ws, ws_bytes, stream, &best);
+}
+
+tctf_status tctf_tuning(tctf_ctx* c, int32_t out[4]) {
+  if (!c || !out) return fail(TCTF_E_ARG, "NULL argument");
+  out[0] = c->knobs.spath;
+  out[1] = c->knobs.chunk;
+  out[2] = c->knobs.ycw;
+  out[3] = c->tuned_from_cache;
+  return TCTF_OK;
 }
 
 tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* omega, const float* X0,
@@ -377,6 +530,7 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
   tctf_ctx* c = new (std::nothrow) tctf_ctx();
   if (!c) return fail(TCTF_E_ARG, "out of host memory");
   s = ctx_init(c, prm, G, omega, X0, Y0, seed, workspace, ws_bytes, hip_stream);
+  if (s == TCTF_OK && prm->autotune) s = autotune(c, prm, G, omega, X0, Y0, seed, workspace, ws_bytes, hip_stream);
   if (s != TCTF_OK) {
     ctx_release(c);
     delete c;
@@ -392,12 +546,17 @@ tctf_status tctf_create(const tctf_params* prm, const float* G, const uint8_t* o
 static tctf_status ensure_graph(tctf_ctx* c) {
   if (c->graph_exec) return TCTF_OK;
   if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  if (!c->br_stream) HIP_TRY(hipStreamCreateWithFlags(&c->br_stream, hipStreamNonBlocking));
+  if (!c->ev_fork) HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  if (!c->ev_join) HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   const hipStream_t user = c->plan.stream;
   c->plan.stream = c->cap_stream;
   hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
   tctf_status s = TCTF_OK;
   if (e == hipSuccess) {
+    c->capturing = true;
     for (int k = 0; k < GRAPH_ITERS && s == TCTF_OK; ++k) s = enqueue_iteration(c);
+    c->capturing = false;
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (s == TCTF_OK && e2 == hipSuccess) {
@@ -744,7 +903,7 @@ tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* me
       case 1: tctf::launch_zgemm(p); break;
       case 2: tctf::launch_agemm(p); break;
       case 3: tctf::launch_hsolve(p); break;
-      case 4: tctf::launch_bgemm(p); break;
+      case 4: tctf::launch_gramx(p); tctf::launch_bgemm(p); break;
       case 5: tctf::launch_ystep(p, 1); break;
       case 6: tctf::launch_pinvy(p, p.stream); break;
       case 7: enqueue_iteration(c); c->iters++; break;

@@ -11,6 +11,7 @@ struct Plan {
   int n1, n2, n3, r, nb;       // nb = n3/2 + 1 stored frequencies
   int nchunk, chunk;           // row chunks of the X~^* W~ reduction
   int ny, ycw;                 // column blocks of the Y-step per frequency, columns per block
+  int spath;                   // slice path: SPATH_COOP, SPATH_THREAD or SPATH_SPLIT
   double mu, rho1, rho2, eta;
   int mixed, force_eigen;
   hipStream_t stream;
@@ -22,6 +23,7 @@ struct Plan {
   float2* yt;       // Y~ [nb][r][n2]
   float2* rhs;      // right-hand side of the H_rho1 solve [nb][r][n1]
   double2* bpart;   // partial X~^* W~ [nb][nchunk][r][n2] (FP64)
+  cd* gxpart;       // partial Grams of X~ over row groups [nb][ngroup][2][r][r] (FP64)
   cd* gxm;          // G_X = X~^* H_rho1 X~ [nb][r][r]
   cd* dmat;         // (H X~)^* (H X~) [nb][r][r]
   cd* gxp;          // G_X^+ [nb][r][r]
@@ -70,17 +72,25 @@ void launch_zero(const Plan& p, void* dst, size_t bytes);
 
 // iteration
 enum SliceMode { SLICE_INIT = 0, SLICE_ITER = 1, SLICE_RESULT = 2, SLICE_KKT = 3 };
+// How steps 3, 4 and 7 run: one fused kernel per OD row with several threads per tube
+// (COOP) or one thread per tube (THREAD), or three launches through spatial buffers (SPLIT).
+enum SlicePath { SPATH_COOP = 1, SPATH_THREAD = 2, SPATH_SPLIT = 3 };
+int slice_default_path(int n2, int n3);
+bool slice_path_valid(int path, int n2, int n3);
 bool slice_supported(int n3);
 bool slice_fused(int n2, int n3);          // the fused LDS slice kernel applies
 void launch_gen_twiddles(const Plan& p);
 void launch_slice_generic(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g);
-bool slice_hosts_pinvy(int n2, int n3);   // the iteration's slice launch also forms G_Y^+
-size_t slice_launch_lds_bytes(int n2, int n3, int r);
+bool slice_hosts_pinvy(const Plan& p);   // the iteration's slice launch also forms G_Y^+
+size_t slice_launch_lds_bytes(const Plan& p);
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g);
 void launch_zgemm(const Plan& p, int with_pinv = 0);   // with_pinv: also G_Y^+ (pinvy_block)
 void launch_agemm(const Plan& p, int raw_a = 0, int advance = 0);   // advance: next rounding-bit counter
 void launch_hsolve(const Plan& p);
-void launch_bgemm(const Plan& p);   // also G_X, G_X^+ and I - eta P_X (gramx_block)
+void launch_bgemm(const Plan& p);   // X~^* W~ chunk partials
+void launch_gramx(const Plan& p);   // G_X, (H X~)^*(H X~), G_X^+ and I - eta P_X
+int gramx_groups(int n1);
+void gramx_set_attr(int r);
 size_t bgemm_lds_bytes(int r, int chunk);
 
 void bgemm_set_attr(size_t lds);

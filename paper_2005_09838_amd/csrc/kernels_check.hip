@@ -119,7 +119,8 @@ __global__ void k_stat_final(const double* __restrict__ part, int nb, const doub
 
 void launch_stationarity(const Plan& p, int w_from_g) {
   launch_agemm(p, 1);   // A = W~ Y~^* into the right-hand-side buffer
-  launch_bgemm(p);      // X~^* W~ partial sums and G_X
+  launch_gramx(p);      // G_X
+  launch_bgemm(p);      // X~^* W~ partial sums
   k_stat_bin<<<p.nb, 256, 0, p.stream>>>(p.xt, p.yt, p.wt, p.rhs, p.bpart, p.gxm, p.stat_work, p.n1,
                                          p.n2, p.n3, p.r, p.nb, p.nchunk, p.rho1, p.mixed);
   launch_zgemm(p);

@@ -347,7 +347,7 @@ void launch_agemm(const Plan& p, int raw_a, int advance) {
 #undef TCTF_AGEMM
 }
 
-// Outputs of gramx_block, per frequency b ([nb][r][r] FP64 complex unless noted).
+// Outputs of the G_X launches, per frequency b ([nb][r][r] FP64 complex unless noted).
 struct GramOut {
   cd* gxm;       // G_X
   cd* dmat;      // (H X~)^*(H X~)
@@ -358,151 +358,109 @@ struct GramOut {
   int force_eigen;
 };
 
-// Rows per staged group of gramx_block (plus the next row): 256, and 64 at r > 16 where the
-// two sweeps need the partials beside the staging area.
-#define GX_ROWS(RM) ((RM) <= 16 ? 256 : 64)
-
-// LDS bytes of gramx_block at rank r <= RM: the staged rows and the complex Gram partials,
-// later G_X with the pseudo-inverse scratch.
-static inline size_t gramx_lds_bytes(int r, int rm) {
-  const int ks = rm == 8 ? 4 : 1;
-  const size_t sb = (size_t)2 * rm * (GX_ROWS(rm) + 4) * sizeof(float);
-  const size_t pb = (size_t)ks * 2 * r * r * sizeof(cd);
-  const size_t a = rm <= 16 ? (sb > pb ? sb : pb) : sb + pb;
-  return a > pinvy_lds_bytes(r) ? a : pinvy_lds_bytes(r);
-}
-
-// Frequency b, by a whole block: the FP64 Grams C = X'^T X' and the same for the row
-// differences X'(i + 1) - X'(i) over all n1 rows, as 16 x 16 x 4 FP64 matrix-core tiles.
-// Rows arrive in groups of GR (plus the next row), staged column by column (X'^T; columns
-// past 2r and rows past n1 zero), the next group's loads in flight while the current one is
-// multiplied.  Within 16 rows the K order is permuted: lane (m, q) feeds rows 4 q .. 4 q + 3
-// of the 16, so one 16-byte LDS read (and one float of the following row) serves four
-// steps.  Full groups need no masks; the last group masks the difference at the last row.
-// At r <= 8 the four wavefronts share the one tile and split the rows; at r > 16 each
-// wavefront takes its four tiles in two sweeps over the rows.  The lanes holding C[2s][2t]
-// gather the 2 x 2 real block by shuffles and form X~^* X~ (s, t) = (C[2s][2t] +
-// C[2s+1][2t+1], C[2s][2t+1] - C[2s+1][2t]), likewise (H X~)^*(H X~); then
-// G_X = X~^* X~ + rho1 (H X~)^*(H X~), its pseudo-inverse (Lemma SVPMPI, pinv_herm) and
-// I - eta P_X.
+// ---------------------------------------------------------------- G_X in two launches
+// k_gramx_part: block (row group g, frequency b) forms over its GXR rows i0 .. i0 + GXR - 1
+// the FP64 partial Grams S_g = sum_i X~(i, :)^* X~(i, :) and, with the next row staged too,
+// D_g = sum_i (X~(i+1, :) - X~(i, :))^* (X~(i+1, :) - X~(i, :)) (no difference past the last
+// row), as the real Gram C = X'^T X' of X'[i][2s + d] = (re, im)_d X~(i, s) on the FP64
+// matrix cores: the rows are staged column by column (X'^T; zeros past n1 and r), and within
+// 16 rows the K order is permuted so that lane (m, q) feeds rows 4q .. 4q + 3, one 16-byte LDS
+// read (and one float of the next row) serving four steps.  At r <= 8 the four wavefronts
+// share the one tile and split the rows; otherwise each takes its tiles.  The lanes holding
+// C[2s][2t] gather the 2 x 2 real block by shuffles: X~^* X~ (s, t) = (C[2s][2t] +
+// C[2s+1][2t+1], C[2s][2t+1] - C[2s+1][2t]), likewise D.
+// k_gramx_inv: per frequency, the partials summed in a fixed order, G_X = S + rho1 D
+// (= X~^* H_rho1 X~), its pseudo-inverse (Lemma SVPMPI, pinv_herm) and I - eta P_X.
+#define GXR 64
 template <int RM>
-__device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1, int r, const GramOut& go,
-                                   unsigned char* sm) {
+__global__ void __launch_bounds__(256) k_gramx_part(const float2* __restrict__ xt, int n1, int r, int ngrp,
+                                                    cd* __restrict__ part) {
   constexpr int MT = RM / 8, NT = MT * MT;         // 16 x 16 tiles of the real Gram
   constexpr int KS = NT >= 4 ? 1 : 4 / NT;         // wavefronts sharing a tile (row split)
   constexpr int TPW = NT >= 4 ? NT / 4 : 1;        // tiles per wavefront
-  constexpr int TPS = TPW < 2 ? TPW : 2;           // tiles per sweep over the rows
-  constexpr int NSW = TPW / TPS;                   // sweeps
-  constexpr int GR = GX_ROWS(RM);                  // rows per group
-  constexpr int LD = GR + 4;                       // LDS stride of a staged column (floats)
-  constexpr int PER = ((GR + 1) * RM + 255) / 256; // staged elements per thread (GR + 1 rows)
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
-  const int rr = r * r, kp = KS > 1 ? w : 0;
-  float* xs = (float*)sm;   // [2 RM][LD]: X'^T, column 2 s + d of X' is row 2 s + d here
-  // [KS][2][rr]: after the staging area, or in it when one sweep leaves it free
-  cd* part = (cd*)(sm + (NSW > 1 ? (size_t)2 * RM * LD * sizeof(float) : 0));
-  // element e of a group: column s = e / (GR + 1), row h = e % (GR + 1); past the matrix: zeros
-  float2 pf[PER];
-  auto load_group = [&](int i0) {
+  constexpr int LD = GXR + 4;                      // LDS stride of a staged column (floats)
+  constexpr int PER = ((GXR + 1) * RM + 255) / 256;
+  __shared__ __align__(16) float xs[2 * RM * LD];
+  __shared__ cd red[KS > 1 ? 2 * KS * RM * RM : 1];
+  const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 15,
+            q = lane >> 4;
+  const int i0 = g * GXR, rr = r * r, kp = KS > 1 ? w : 0;
+  const int nrows = min(GXR, n1 - i0);
+  {
+    float2 pf[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int e = tid + 256 * u, s = e / (GR + 1), h = e % (GR + 1);
+      const int e = tid + 256 * u, s = e / (GXR + 1), h = e % (GXR + 1);
       pf[u] = ld_or(xt, ((size_t)b * r + s) * n1 + i0 + h, s < r && i0 + h < n1, make_float2(0.f, 0.f));
     }
-  };
-  load_group(0);
 #pragma unroll
-  for (int sw = 0; sw < NSW; ++sw) {
-    v4d acs[TPS], acd[TPS];
-#pragma unroll
-    for (int u = 0; u < TPS; ++u) {
-      acs[u] = v4d{0.0, 0.0, 0.0, 0.0};
-      acd[u] = v4d{0.0, 0.0, 0.0, 0.0};
-    }
-    for (int i0 = 0; i0 < n1; i0 += GR) {
-      const int nrows = min(GR, n1 - i0);
-      __syncthreads();   // the previous rows are consumed
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int e = tid + 256 * u, s = e / (GR + 1), h = e % (GR + 1);
-        if (s < RM) {
-          xs[(2 * s) * LD + h] = pf[u].x;
-          xs[(2 * s + 1) * LD + h] = pf[u].y;
-        }
-      }
-      __syncthreads();
-      if (i0 + GR < n1) load_group(i0 + GR);
-      else if (sw + 1 < NSW) load_group(0);
-      const bool full = i0 + GR < n1;   // GR rows and the next one: no masks
-#pragma unroll
-      for (int u = 0; u < TPS; ++u) {
-        const int tile = KS > 1 ? 0 : w + 4 * (sw * TPS + u);
-        const float* pa = xs + (16 * (tile / MT) + m) * LD;   // column 2 s + d of X'
-        const float* pb = xs + (16 * (tile % MT) + m) * LD;
-        auto step16 = [&](int jb, auto masked) {
-          const int h0 = 16 * jb + 4 * q;
-          const float4 a4 = *(const float4*)(pa + h0), b4 = *(const float4*)(pb + h0);
-          const double av[5] = {a4.x, a4.y, a4.z, a4.w, pa[h0 + 4]};
-          const double bv[5] = {b4.x, b4.y, b4.z, b4.w, pb[h0 + 4]};
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) {
-            double a1 = av[jj + 1] - av[jj], b1 = bv[jj + 1] - bv[jj];
-            if constexpr (decltype(masked)::value) {   // no difference at the last row
-              if (i0 + h0 + jj + 1 >= n1) a1 = b1 = 0.0;
-            }
-            acs[u] = mfma4d(av[jj], bv[jj], acs[u]);
-            acd[u] = mfma4d(a1, b1, acd[u]);
-          }
-        };
-        if (full) {
-#pragma unroll 2
-          for (int jb = kp; jb < GR / 16; jb += KS) step16(jb, std::false_type{});
-        } else {
-          for (int jb = kp; 16 * jb < nrows; jb += KS) step16(jb, std::true_type{});
-        }
-      }
-    }
-    if (NSW == 1) __syncthreads();   // the partials take the staging area
-    // element t of a lane: real row 16 ta + q + 4 t, column 16 tb + m; the lanes with q and m
-    // even hold C[2s][2t] and read C[2s][2t+1], C[2s+1][2t], C[2s+1][2t+1] from lanes + 1,
-    // + 16 and + 17
-#pragma unroll
-    for (int u = 0; u < TPS; ++u) {
-      const int tile = KS > 1 ? 0 : w + 4 * (sw * TPS + u), ta = tile / MT, tb = tile % MT;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const double s0 = acs[u][t], s1 = __shfl_down(s0, 1), s16 = __shfl_down(s0, 16),
-                     s17 = __shfl_down(s0, 17);
-        const double d0 = acd[u][t], d1 = __shfl_down(d0, 1), d16 = __shfl_down(d0, 16),
-                     d17 = __shfl_down(d0, 17);
-        const int sr = (16 * ta + q + 4 * t) >> 1, sc = (16 * tb + m) >> 1;
-        if (!(q & 1) && !(m & 1) && sr < r && sc < r) {
-          part[(2 * kp) * rr + sr * r + sc] = cd_make(s0 + s17, s1 - s16);
-          part[(2 * kp + 1) * rr + sr * r + sc] = cd_make(d0 + d17, d1 - d16);
-        }
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, s = e / (GXR + 1), h = e % (GXR + 1);
+      if (s < RM) {
+        xs[(2 * s) * LD + h] = pf[u].x;
+        xs[(2 * s + 1) * LD + h] = pf[u].y;
       }
     }
   }
   __syncthreads();
-  constexpr int GPT = (RM * RM + 255) / 256;   // G_X entries per thread
-  cd gv[GPT];
+  v4d acs[TPW], acd[TPW];
 #pragma unroll
-  for (int k = 0; k < GPT; ++k) {
-    const int e = tid + 256 * k;
-    gv[k] = cd_make(0.0, 0.0);
-    if (e < rr) {
-      cd sv = part[e], dv = part[rr + e];
+  for (int tu = 0; tu < TPW; ++tu) {
+    acs[tu] = v4d{0.0, 0.0, 0.0, 0.0};
+    acd[tu] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int tile = KS > 1 ? 0 : w + 4 * tu;
+    const float* pa = xs + (16 * (tile / MT) + m) * LD;   // column 2 s + d of X'
+    const float* pb = xs + (16 * (tile % MT) + m) * LD;
+    for (int jb = kp; 16 * jb < nrows; jb += KS) {
+      const int h0 = 16 * jb + 4 * q;
+      const float4 a4 = *(const float4*)(pa + h0), b4 = *(const float4*)(pb + h0);
+      const double av[5] = {a4.x, a4.y, a4.z, a4.w, pa[h0 + 4]};
+      const double bv[5] = {b4.x, b4.y, b4.z, b4.w, pb[h0 + 4]};
 #pragma unroll
-      for (int j = 1; j < KS; ++j) {   // the row parts, in a fixed order
-        sv = cd_add(sv, part[2 * j * rr + e]);
-        dv = cd_add(dv, part[(2 * j + 1) * rr + e]);
+      for (int jj = 0; jj < 4; ++jj) {
+        const bool dif = i0 + h0 + jj + 1 < n1;   // the row pair (i, i + 1) exists
+        const double a1 = dif ? av[jj + 1] - av[jj] : 0.0, b1 = dif ? bv[jj + 1] - bv[jj] : 0.0;
+        acs[tu] = mfma4d(av[jj], bv[jj], acs[tu]);
+        acd[tu] = mfma4d(a1, b1, acd[tu]);
       }
-      gv[k] = cd_add(sv, cd_scale(dv, go.rho1));
-      go.gxm[(size_t)b * rr + e] = gv[k];
-      go.dmat[(size_t)b * rr + e] = dv;
     }
   }
-  __syncthreads();   // the partials are read; G_X and the pinv scratch take their place
+  // element t of lane (q, m): real row 16 ta + q + 4 t, column 16 tb + m
+  cd* out = part + (size_t)(b * ngrp + g) * 2 * rr;
+#pragma unroll
+  for (int tu = 0; tu < TPW; ++tu) {
+    const int tile = KS > 1 ? 0 : w + 4 * tu, ta = tile / MT, tb = tile % MT;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double s0 = acs[tu][t], s1 = __shfl_down(s0, 1), s16 = __shfl_down(s0, 16), s17 = __shfl_down(s0, 17);
+      const double d0 = acd[tu][t], d1 = __shfl_down(d0, 1), d16 = __shfl_down(d0, 16), d17 = __shfl_down(d0, 17);
+      const int sr = (16 * ta + q + 4 * t) >> 1, sc = (16 * tb + m) >> 1;
+      if (!(q & 1) && !(m & 1) && sr < r && sc < r) {
+        const cd vs = cd_make(s0 + s17, s1 - s16), vd = cd_make(d0 + d17, d1 - d16);
+        if (KS > 1) {
+          red[(2 * kp) * rr + sr * r + sc] = vs;
+          red[(2 * kp + 1) * rr + sr * r + sc] = vd;
+        } else {
+          out[sr * r + sc] = vs;
+          out[rr + sr * r + sc] = vd;
+        }
+      }
+    }
+  }
+  if constexpr (KS > 1) {
+    __syncthreads();
+    for (int e = tid; e < 2 * rr; e += 256) {
+      const int which = e / rr, k = e % rr;
+      cd v = red[which * rr + k];
+      for (int j = 1; j < KS; ++j) v = cd_add(v, red[(2 * j + which) * rr + k]);   // fixed order
+      out[e] = v;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gramx_inv(const cd* __restrict__ part, int ngrp, int r, GramOut go) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const int b = blockIdx.x, tid = threadIdx.x, rr = r * r;
   cd* gx = (cd*)sm;
   cd* gp = gx + rr;
   PinvScratch ps;
@@ -512,10 +470,17 @@ __device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1,
   ps.rowk = ps.colk + r;
   ps.rot = (double*)(ps.rowk + r);
   ps.red = ps.rot + 96;
-#pragma unroll
-  for (int k = 0; k < GPT; ++k) {
-    const int e = tid + 256 * k;
-    if (e < rr) gx[e] = gv[k];
+  for (int e = tid; e < rr; e += 256) {
+    cd sv = cd_make(0.0, 0.0), dv = cd_make(0.0, 0.0);
+    for (int g = 0; g < ngrp; ++g) {   // fixed order
+      const cd* pg = part + (size_t)(b * ngrp + g) * 2 * rr;
+      sv = cd_add(sv, pg[e]);
+      dv = cd_add(dv, pg[rr + e]);
+    }
+    const cd gv = cd_add(sv, cd_scale(dv, go.rho1));
+    go.gxm[(size_t)b * rr + e] = gv;
+    go.dmat[(size_t)b * rr + e] = dv;
+    gx[e] = gv;
   }
   __syncthreads();
   const int fullr = pinv_herm(gx, gp, r, go.force_eigen, ps);
@@ -532,7 +497,33 @@ __device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1,
   if (tid == 0) go.qx_zero[b] = qzero ? 1 : 0;
 }
 
-// ---------------------------------------------------------------- X~^* W~, and G_X with its inverse
+int gramx_groups(int n1) { return (n1 + GXR - 1) / GXR; }
+
+void gramx_set_attr(int r) {
+  if (pinvy_lds_bytes(r) > 65536)
+    (void)hipFuncSetAttribute((const void*)k_gramx_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)pinvy_lds_bytes(r));
+}
+
+void launch_gramx(const Plan& p) {
+  GramOut go;
+  go.gxm = p.gxm;
+  go.dmat = p.dmat;
+  go.gxp = p.gxp;
+  go.qx = p.qx;
+  go.qx_zero = p.qx_zero;
+  go.rho1 = p.rho1;
+  go.eta = p.eta;
+  go.force_eigen = p.force_eigen;
+  const int ngrp = gramx_groups(p.n1);
+  const dim3 grid(ngrp, p.nb);
+  if (p.r <= 8) k_gramx_part<8><<<grid, 256, 0, p.stream>>>(p.xt, p.n1, p.r, ngrp, p.gxpart);
+  else if (p.r <= 16) k_gramx_part<16><<<grid, 256, 0, p.stream>>>(p.xt, p.n1, p.r, ngrp, p.gxpart);
+  else k_gramx_part<32><<<grid, 256, 0, p.stream>>>(p.xt, p.n1, p.r, ngrp, p.gxpart);
+  k_gramx_inv<<<p.nb, 256, pinvy_lds_bytes(p.r), p.stream>>>(p.gxpart, ngrp, p.r, go);
+}
+
+// ---------------------------------------------------------------- X~^* W~
 // Real form: C'[2s + d][2j + c] = sum_i X'[2s + d][i] W'[i][2j + c] with X'[2s + d][i] =
 // (re, im)_d X~(i, s) and W' the interleaved W~ rows; then
 // (X~^* W~)(s, j) = (C'[2s][2j] + C'[2s+1][2j+1], C'[2s][2j+1] - C'[2s+1][2j]).
@@ -540,30 +531,18 @@ __device__ inline void gramx_block(int b, const float2* __restrict__ xt, int n1,
 // of BG_COLS columns, its whole W~ slab are staged in LDS with every load of a thread
 // issued at once; each wavefront owns a quarter of the 16-column tiles of a pass, on the
 // FP64 matrix cores.
-// At r <= 16 the first nb blocks of the launch instead form, for frequency blockIdx.x, the
-// whole Gram G_X = X~^* X~ + rho1 (H X~)^*(H X~) in FP64 on the matrix cores, its
-// pseudo-inverse and I - eta P_X (gramx_block), beside the products; at r > 16 k_gramx
-// does this work in a launch of its own.
 #define BG_COLS 64                  // complex columns per pass
 #define BG_MAXROWS 64               // rows per chunk at most
 #define BG_WLD (2 * BG_COLS + 16)   // LDS row stride of the staged W~ slab (floats)
-template <int RM>   // r <= RM; registers and LDS allow three blocks per compute unit at r <= 16
+template <int RM>   // r <= RM
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RM <= 16 ? 2 : 1)))
-k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, double2* __restrict__ bpart, GramOut go, int n1,
+k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, double2* __restrict__ bpart, int n1,
         int n2, int r, int nb, int nchunk, int chunk, int mixed) {
   extern __shared__ __align__(16) float smb[];
-  constexpr bool GRAM = RM <= 16;   // at r > 16 the registers of both paths would not fit twice
-  const int ng = GRAM ? nb : 0;   // G_X blocks at the front of the grid
-  if constexpr (GRAM) {
-    if ((int)blockIdx.x < ng) {
-      gramx_block<RM>(blockIdx.x, xt, n1, r, go, (unsigned char*)smb);
-      return;
-    }
-  }
   const int xld = 2 * r + 16;                    // LDS row stride of the staged X~ rows (floats)
   float* xs = smb;                               // [chunk + 1][xld]: (re, im) of X~(i, s) at 2 s
   float* ws = smb + (size_t)(chunk + 1) * xld;   // [chunk rounded up to 4][BG_WLD]
-  const int c = ((int)blockIdx.x - ng) % nchunk, b = ((int)blockIdx.x - ng) / nchunk, tid = threadIdx.x;
+  const int c = (int)blockIdx.x % nchunk, b = (int)blockIdx.x / nchunk, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
   const int i0 = c * chunk, i1 = min(n1, i0 + chunk), nrows = i1 - i0;
   const int rows = nrows;
@@ -662,21 +641,9 @@ k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, double2* __r
   }
 }
 
-// G_X alone, one block per frequency (r > 16: beside the products it would cost them
-// registers).
-template <int RM>
-__global__ void __launch_bounds__(256) k_gramx(const float2* __restrict__ xt, GramOut go, int n1, int r) {
-  extern __shared__ __align__(16) unsigned char smg[];
-  gramx_block<RM>(blockIdx.x, xt, n1, r, go, smg);
-}
-
-
 size_t bgemm_lds_bytes(int r, int chunk) {
-  const int rm = r <= 8 ? 8 : (r <= 16 ? 16 : 32);
   const size_t slab = (size_t)((chunk + 3) / 4 * 4) * BG_WLD * sizeof(float);
-  const size_t chunkb = (size_t)(chunk + 1) * (2 * r + 16) * sizeof(float) + slab;
-  const size_t gram = gramx_lds_bytes(r, rm);
-  return chunkb > gram ? chunkb : gram;
+  return (size_t)(chunk + 1) * (2 * r + 16) * sizeof(float) + slab;
 }
 
 void bgemm_set_attr(size_t lds) {
@@ -684,34 +651,19 @@ void bgemm_set_attr(size_t lds) {
     (void)hipFuncSetAttribute((const void*)k_bgemm<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute((const void*)k_bgemm<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipFuncSetAttribute((const void*)k_bgemm<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)k_gramx<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
 }
 
+// X~^* W~ chunk partials only (G_X: launch_gramx).
 void launch_bgemm(const Plan& p) {
-  const bool fused = p.r <= 16;
-  const int grid = (fused ? p.nb : 0) + p.nchunk * p.nb;   // G_X blocks first, then (chunk, frequency)
+  const int grid = p.nchunk * p.nb;   // (chunk, frequency)
   const size_t lds = bgemm_lds_bytes(p.r, p.chunk);
-  GramOut go;
-  go.gxm = p.gxm;
-  go.dmat = p.dmat;
-  go.gxp = p.gxp;
-  go.qx = p.qx;
-  go.qx_zero = p.qx_zero;
-  go.rho1 = p.rho1;
-  go.eta = p.eta;
-  go.force_eigen = p.force_eigen;
 #define TCTF_BGEMM(RM)                                                                                  \
-  k_bgemm<RM><<<grid, 256, lds, p.stream>>>(p.wt, p.xt, p.bpart, go, p.n1, p.n2, p.r, p.nb, p.nchunk, \
-                                            p.chunk, p.mixed)
-  if (p.r <= 8) {
-    TCTF_BGEMM(8);
-  } else if (p.r <= 16) {
-    TCTF_BGEMM(16);
-  } else {
-    k_gramx<32><<<p.nb, 256, lds, p.stream>>>(p.xt, go, p.n1, p.r);
-    TCTF_BGEMM(32);
-  }
+  k_bgemm<RM><<<grid, 256, lds, p.stream>>>(p.wt, p.xt, p.bpart, p.n1, p.n2, p.r, p.nb, p.nchunk, p.chunk, \
+                                            p.mixed)
+  if (p.r <= 8) TCTF_BGEMM(8);
+  else if (p.r <= 16) TCTF_BGEMM(16);
+  else TCTF_BGEMM(32);
 #undef TCTF_BGEMM
 }
 

@@ -673,21 +673,35 @@ void slice_set_attr(int n3, size_t lds) {
 
 bool slice_fused(int n2, int n3) { return slice_supported(n3) && slice_lds_bytes(n2, n3) <= TCTF_SLICE_LDS_MAX; }
 
-bool slice_hosts_pinvy(int n2, int n3) { return slice_fused(n2, n3) && coop_threads(n2, n3) > 0; }
+int slice_default_path(int n2, int n3) {
+  if (!slice_fused(n2, n3)) return SPATH_SPLIT;
+  return coop_threads(n2, n3) > 0 ? SPATH_COOP : SPATH_THREAD;
+}
 
-size_t slice_launch_lds_bytes(int n2, int n3, int r) {
-  if (!slice_fused(n2, n3)) return 0;
-  const size_t a = slice_lds_bytes(n2, n3), b = slice_hosts_pinvy(n2, n3) ? pinvy_lds_bytes(r) : 0;
+bool slice_path_valid(int path, int n2, int n3) {
+  switch (path) {
+    case SPATH_COOP: return slice_fused(n2, n3) && coop_threads(n2, n3) > 0;
+    case SPATH_THREAD: return slice_fused(n2, n3);
+    case SPATH_SPLIT: return true;
+    default: return false;
+  }
+}
+
+bool slice_hosts_pinvy(const Plan& p) { return p.spath == SPATH_COOP; }
+
+size_t slice_launch_lds_bytes(const Plan& p) {
+  if (p.spath == SPATH_SPLIT) return 0;
+  const size_t a = slice_lds_bytes(p.n2, p.n3), b = p.spath == SPATH_COOP ? pinvy_lds_bytes(p.r) : 0;
   return a > b ? a : b;
 }
 
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g) {
-  if (!slice_fused(p.n2, p.n3)) {
+  if (p.spath == SPATH_SPLIT) {
     launch_slice_generic(p, mode, w_out, z_out, w_from_g);
     return;
   }
   SliceArgs a;
-  a.npinv = (mode == SLICE_ITER && slice_hosts_pinvy(p.n2, p.n3)) ? p.nb : 0;
+  a.npinv = (mode == SLICE_ITER && slice_hosts_pinvy(p)) ? p.nb : 0;
   a.pa = pinvy_args(p);
   a.ctr = p.ctr;
   a.zt = p.zt;
@@ -707,8 +721,8 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
   a.mode = mode;
   a.mixed = p.mixed;
   a.w_from_g = w_from_g;
-  const size_t lds = slice_launch_lds_bytes(p.n2, p.n3, p.r);
-  const int coop = coop_threads(p.n2, p.n3);
+  const size_t lds = slice_launch_lds_bytes(p);
+  const int coop = p.spath == SPATH_COOP ? coop_threads(p.n2, p.n3) : 0;
   if (coop > 0) {
     switch (p.n3) {
 #define TCTF_CASE(n)                                                                                   \

@@ -172,3 +172,50 @@ def test_batch_member_against_oracle():
     st2, _ = oracle_run(d2, 2, 12)
     assert rel(b[1].result()["W"].cpu().numpy(), st2.w) < 1e-5
     b.close()
+
+
+@pytest.mark.parametrize("n1,n2,n3,r", [(36, 48, 7, 3), (40, 65, 28, 6), (30, 300, 28, 4), (20, 15, 17, 3)])
+def test_autotuned_execution_shape(n1, n2, n3, r):
+    """tctf_params.autotune: the chosen slice path is one the sizes allow, the result stays on
+    the oracle's trajectory, and a second context of the same shape takes the cached choice
+    and gives the same bits."""
+    from paper_2005_09838_amd import Completion
+    d = make_inputs(n1, n2, n3, r, p=0.4, seed=n1 + n2, weekly=True)
+    mk = lambda: Completion(to_dev(d["G"]), to_dev(d["omega"]), r, X0=to_dev(d["X0"]), Y0=to_dev(d["Y0"]),
+                            autotune=True)
+    a = mk()
+    ta = a.tuning()
+    assert ta[0] in (1, 2, 3) and ta[1] % 16 == 0 and 16 <= ta[1] <= 64 and ta[2] >= 1
+    a.step(8)
+    wa = a.result()["W"].cpu().numpy()
+    b = mk()
+    tb = b.tuning()
+    assert tb[:3] == ta[:3] and tb[3] == 1
+    b.step(8)
+    assert np.array_equal(b.result()["W"].cpu().numpy(), wa)
+    st, _ = oracle_run(d, r, 8)
+    print(f"{n1}x{n2}x{n3} r{r}: tuning {ta} rel {rel(wa, st.w):.2e}", flush=True)
+    assert rel(wa, st.w) < 1e-5
+    a.close()
+    b.close()
+
+
+def test_batch_of_autotuned_members_matches_single_runs():
+    """Members with autotune: the batch gives, bit for bit, what autotuned single contexts give."""
+    from paper_2005_09838_amd import Batch, Completion
+    shapes = [(36, 48, 7, 3, 0.3), (20, 30, 12, 4, 0.5), (64, 24, 28, 6, 0.4), (30, 300, 28, 4, 0.4)]
+    probs, data = [], []
+    for k, (n1, n2, n3, r, p) in enumerate(shapes):
+        d = make_inputs(n1, n2, n3, r, p=p, seed=90 + k, weekly=True)
+        data.append((d, r))
+        probs.append({"G": to_dev(d["G"]), "omega": to_dev(d["omega"]), "r": r, "X0": to_dev(d["X0"]),
+                      "Y0": to_dev(d["Y0"]), "autotune": True})
+    b = Batch(probs)
+    b.step(13)
+    for k, (d, r) in enumerate(data):
+        c = Completion(to_dev(d["G"]), to_dev(d["omega"]), r, X0=to_dev(d["X0"]), Y0=to_dev(d["Y0"]), autotune=True)
+        c.step(13)
+        assert c.tuning()[:3] == b[k].tuning()[:3]
+        assert np.array_equal(b[k].result()["W"].cpu().numpy(), c.result()["W"].cpu().numpy()), k
+        c.close()
+    b.close()
