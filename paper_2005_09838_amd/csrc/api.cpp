@@ -338,7 +338,7 @@ static tctf_status enqueue_iteration(tctf_ctx* c) {
   }
   if (s == TCTF_OK) s = stage(c, 5, [&] { tctf::launch_ystep(p, 0); });
   // Z~ = X~Y~; G_Y^+ and I - eta P_Y for the next X-step ride along in extra blocks of the
-  // cooperative slice launch, or of this launch where the slice runs the per-thread kernel
+  // cooperative slice launch, or of this launch on the other slice paths
   if (s == TCTF_OK) s = stage(c, 1, [&] { tctf::launch_zgemm(p, tctf::slice_hosts_pinvy(p) ? 0 : 1); });
   if (s == TCTF_OK) s = stage(c, 0, [&] { tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0); });
   // step 5 after iterations rank_every, 2 rank_every, ... (c->iters counts the iterations
