@@ -11,6 +11,20 @@
       (KiB) of the kernel, each scaled by the ratio of the known bytes of a plain copy
       kernel to what the same counter reads for it.  The summary records the SHA-256 of the
       kernel sources it was taken from, so a later reader can tell whether it still applies.
+
+  python -m paper_2005_09838_amd.profile_summary all-traffic --fetch DIR --write DIR
+         --copy-fetch DIR --copy-write DIR --copy-bytes N --per-iteration PATTERN ...
+         --algorithmic-bytes B --title T --command CMD --out FILE
+      the same scaled counter bytes for every kernel of a run, and their sum over the kernels
+      launched once per iteration (the PATTERN list), against the iteration's algorithmic bytes.
+
+  python -m paper_2005_09838_amd.profile_summary mfma --counters DIR --stats DIR
+         --title T --command CMD --out FILE
+      matrix-core use per kernel from a run that collected SQ_INSTS_VALU_MFMA_MOPS_F32,
+      SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE: flops per
+      dispatch (each MOPS unit is 512 flops), the rate over the kernel's mean duration from a
+      kernel-trace run against the dense peak of its type, and the matrix-core busy share
+      (busy cycles over that duration's cycles at 2.4 GHz times the chip's 1024 SIMDs).
 """
 from __future__ import annotations
 
@@ -127,6 +141,87 @@ def write_traffic(a) -> None:
         f.write("\n".join(lines) + "\n")
 
 
+def _scales(a):
+    kib = 1024.0
+    _, cfetch, _ = _pick(counter_means(a.copy_fetch, "FETCH_SIZE"), a.copy_kernel)
+    _, cwrite, _ = _pick(counter_means(a.copy_write, "WRITE_SIZE"), a.copy_kernel)
+    return cfetch, cwrite, a.copy_bytes / (cfetch * kib), a.copy_bytes / (cwrite * kib)
+
+
+def write_all_traffic(a) -> None:
+    kib = 1024.0
+    fetch = counter_means(a.fetch, "FETCH_SIZE")
+    write = counter_means(a.write, "WRITE_SIZE")
+    cfetch, cwrite, f_fetch, f_write = _scales(a)
+    lines = [a.title, f"source_sha256: {source_digest()}",
+             f"copy kernel: {a.copy_bytes:.0f} bytes each way; counter reads fetch {cfetch:.1f} KiB, "
+             f"write {cwrite:.1f} KiB; scales {f_fetch:.4f} (fetch), {f_write:.4f} (write)", "",
+             f"{'kernel':44s} {'dispatches':>10s} {'fetch_MB':>9s} {'write_MB':>9s} {'total_MB':>9s}"]
+    total = 0.0
+    rows = []
+    for k in sorted(set(fetch) & set(write)):
+        fb = fetch[k][0] * kib * f_fetch / 1e6
+        wb = write[k][0] * kib * f_write / 1e6
+        rows.append((fb + wb, k, fb, wb, fetch[k][1]))
+    rows.sort(reverse=True)
+    for t, k, fb, wb, n in rows:
+        lines.append(f"{_short(k)[:44]:44s} {n:10d} {fb:9.2f} {wb:9.2f} {t:9.2f}")
+    picked = []
+    for pat in a.per_iteration:
+        cands = [r for r in rows if pat in r[1]]
+        if not cands:
+            raise SystemExit(f"no kernel matching {pat!r}")
+        best = max(cands, key=lambda r: r[4])
+        picked.append(best)
+        total += best[0]
+    lines += ["", "once per iteration: " + ", ".join(_short(r[1]) for r in picked),
+              f"counter_bytes_per_iteration_MB: {total:.2f}",
+              f"algorithmic_bytes_per_iteration_MB: {a.algorithmic_bytes / 1e6:.2f}",
+              f"counter_over_algorithmic: {total * 1e6 / a.algorithmic_bytes:.3f}", "commands:"]
+    lines += [f"  {c}" for c in a.command]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+MFMA_PEAK_TFLOPS = {"F32": 157.3, "F64": 78.6}
+SIMDS = 1024          # 256 compute units x 4 SIMDs
+CLOCK_HZ = 2.4e9      # peak engine clock
+
+
+def write_mfma(a) -> None:
+    f32 = counter_means(a.counters, "SQ_INSTS_VALU_MFMA_MOPS_F32")
+    f64 = counter_means(a.counters, "SQ_INSTS_VALU_MFMA_MOPS_F64")
+    busy = counter_means(a.counters, "SQ_VALU_MFMA_BUSY_CYCLES")
+    dur_ns = {r["Name"]: float(r["AverageNs"]) for r in kernel_stats(a.stats)}
+    lines = [a.title, f"source_sha256: {source_digest()}", "",
+             f"{'kernel':40s} {'disp':>5s} {'GFLOP_f32':>9s} {'GFLOP_f64':>9s} {'mean_us':>8s} "
+             f"{'TFLOP/s':>8s} {'of_peak':>8s} {'busy%':>6s}"]
+    rows = []
+    for k in f32:
+        fl32 = f32[k][0] * 512 / 1e9
+        fl64 = f64.get(k, (0.0, 0))[0] * 512 / 1e9
+        if fl32 + fl64 == 0.0 or k not in dur_ns:
+            continue
+        ns = dur_ns[k]
+        rate = (fl32 + fl64) / ns   # GFLOP per ns = 1e18 FLOP/s; in TFLOP/s below
+        rate_tf = rate * 1e6
+        peak = (fl32 * MFMA_PEAK_TFLOPS["F32"] + fl64 * MFMA_PEAK_TFLOPS["F64"]) / (fl32 + fl64)
+        util = 100.0 * busy.get(k, (0.0, 0))[0] / (ns * 1e-9 * CLOCK_HZ * SIMDS)
+        rows.append((fl32 + fl64, f"{_short(k)[:40]:40s} {f32[k][1]:5d} {fl32:9.4f} {fl64:9.4f} {ns / 1e3:8.2f} "
+                                  f"{rate_tf:8.2f} {rate_tf / peak:8.4f} {util:6.2f}"))
+    rows.sort(reverse=True)
+    lines += [r[1] for r in rows]
+    lines += ["",
+              "GFLOP: SQ_INSTS_VALU_MFMA_MOPS_* x 512 per dispatch (counter run); mean_us: the kernel's",
+              "mean duration in the kernel-trace run; of_peak: against dense MFMA FP32 157.3 TFLOP/s,",
+              "FP64 78.6 TFLOP/s; busy%: SQ_VALU_MFMA_BUSY_CYCLES over mean duration x 2.4 GHz x 1024 SIMDs",
+              "(GRBM_GUI_ACTIVE of a counter-run dispatch includes the profiler's serialisation, so it",
+              "is not used as the denominator)",
+              "commands:"] + [f"  {c}" for c in a.command]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="what", required=True)
@@ -141,11 +236,27 @@ def main() -> None:
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--algorithmic-bytes", type=float, required=True)
     t.add_argument("--command", action="append", required=True)
+    t = sub.add_parser("all-traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "title", "out"):
+        t.add_argument("--" + k.replace("_", "-"), required=True)
+    t.add_argument("--copy-kernel", default="elementwise")
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--algorithmic-bytes", type=float, required=True)
+    t.add_argument("--per-iteration", nargs="+", required=True)
+    t.add_argument("--command", action="append", required=True)
+    m = sub.add_parser("mfma")
+    for k in ("counters", "stats", "title", "out"):
+        m.add_argument("--" + k, required=True)
+    m.add_argument("--command", action="append", required=True)
     a = ap.parse_args()
     if a.what == "stats":
         write_stats(a.directory, a.command, a.out)
-    else:
+    elif a.what == "traffic":
         write_traffic(a)
+    elif a.what == "all-traffic":
+        write_all_traffic(a)
+    else:
+        write_mfma(a)
 
 
 if __name__ == "__main__":
