@@ -86,8 +86,8 @@ typedef struct {
                            and batches refuse the context                                   */
   int32_t autotune;     /* 1: tctf_create times the execution shapes this problem allows (the
                            fusion depth of steps 3, 4 and 7: one fused kernel per OD row with
-                           several or one thread per tube, or three launches; rows per
-                           X~^* W~ chunk; columns per Y-step block) and keeps the fastest,
+                           several or one thread per tube, or three launches; columns
+                           per X~^* W~ block; columns per Y-step block) and keeps the fastest,
                            remembered per shape and device for the process (later contexts
                            of the shape reuse it); the workspace is sized for every shape.
                            Shapes change summation orders only.  0 (default): fixed rules.
@@ -185,7 +185,7 @@ tctf_status tctf_set_state(tctf_ctx* c, const void* src, size_t bytes);
 tctf_status tctf_rank_vector(tctf_ctx* c, int32_t* ranks);
 
 /* The execution shape in use: out[0] = slice path (1 fused, several threads per tube;
- * 2 fused, one thread per tube; 3 three launches), out[1] = rows per X~^* W~ chunk,
+ * 2 fused, one thread per tube; 3 three launches), out[1] = columns per X~^* W~ block,
  * out[2] = columns per Y-step block, out[3] = 1 if it came from the process's tuning cache. */
 tctf_status tctf_tuning(tctf_ctx* c, int32_t out[4]);
 

@@ -367,7 +367,7 @@ class Completion:
         return tctf_stationarity(self.ctx)
 
     def tuning(self):
-        """(slice path, rows per X~^* W~ chunk, columns per Y-step block, from the cache)."""
+        """(slice path, columns per X~^* W~ block, columns per Y-step block, from the cache)."""
         return tctf_tuning(self.ctx)
 
     def rank_vector(self):

@@ -60,35 +60,26 @@ struct Layout {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static void chunking(int n1, int nb, int* nchunk, int* chunk) {
-  // aim at >= 512 blocks for the X~^* W~ reduction, rows per chunk a multiple of 16
-  int want = (512 + nb - 1) / nb;
-  int maxc = (n1 + 31) / 32;
-  int nc = want < maxc ? want : maxc;
-  const int minc = (n1 + 63) / 64;   // at most 64 rows per chunk (the staged W~ slab)
-  if (nc < minc) nc = minc;
-  if (nc < 1) nc = 1;
-  int ch = (n1 + nc - 1) / nc;
-  ch = ((ch + 15) / 16) * 16;
-  nc = (n1 + ch - 1) / ch;
-  *nchunk = nc;
-  *chunk = ch;
+// Complex columns per X~^* W~ block: 32 (fewer re-reads of X~) when that still gives at
+// least 256 blocks, else 16.
+static int default_bcg(int n2, int nb, int r) {
+  (void)r;
+  return (long)((n2 + 31) / 32) * nb >= 256 ? 32 : 16;
 }
 
 // Tunable execution shape of one context: the slice path (tctf::SlicePath, the fusion
-// depth of steps 3, 4 and 7), the rows per X~^* W~ chunk and the columns per Y-step block.
+// depth of steps 3, 4 and 7), the columns per X~^* W~ block and per Y-step block.
 struct Knobs {
-  int spath, chunk, ycw;
+  int spath, bcg, ycw;
 };
-#define TUNE_MIN_CHUNK 16
 #define TUNE_MIN_YCW 8
 
 static Knobs default_knobs(const tctf_params& p) {
   Knobs k;
-  int nchunk, ny;
+  int ny;
   const int nb = p.n3 / 2 + 1;
   k.spath = tctf::slice_default_path(p.n2, p.n3);
-  chunking(p.n1, nb, &nchunk, &k.chunk);
+  k.bcg = default_bcg(p.n2, nb, p.r);
   tctf::ystep_split(p.n2, p.r, nb, &ny, &k.ycw);
   return k;
 }
@@ -98,9 +89,8 @@ static Layout make_layout(const tctf_params& p) {
   const size_t n1 = p.n1, n2 = p.n2, n3 = p.n3, r = p.r, nb = n3 / 2 + 1;
   // buffers sized for the default shape, or for every shape the autotuner may pick
   const Knobs dk = default_knobs(p);
-  const int chunk = p.autotune ? TUNE_MIN_CHUNK : dk.chunk;
   const int ycw = p.autotune ? (TUNE_MIN_YCW < p.n2 ? TUNE_MIN_YCW : p.n2) : dk.ycw;
-  const size_t nchunk = (n1 + chunk - 1) / chunk, ny = (n2 + ycw - 1) / ycw;
+  const size_t ny = (n2 + ycw - 1) / ycw;
   const size_t welem = p.precision == TCTF_MIXED_BF16 ? 4 : 8;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
@@ -110,7 +100,7 @@ static Layout make_layout(const tctf_params& p) {
   L.xt = take(nb * r * n1 * 8);
   L.yt = take(nb * r * n2 * 8);
   L.rhs = take(nb * r * n1 * 8);
-  L.bpart = take(nb * nchunk * r * n2 * 16);
+  L.bpart = take(nb * r * n2 * 16);
   L.gxpart = take(nb * (size_t)tctf::gramx_groups(p.n1) * 2 * r * r * 16);
   L.gxm = take(nb * r * r * 16);
   L.dmat = take(nb * r * r * 16);
@@ -234,8 +224,7 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.r = p.r;
   q.nb = p.n3 / 2 + 1;
   q.spath = c->knobs.spath;
-  q.chunk = c->knobs.chunk;
-  q.nchunk = (p.n1 + q.chunk - 1) / q.chunk;
+  q.bcg = c->knobs.bcg;
   q.ycw = c->knobs.ycw;
   q.ny = (p.n2 + q.ycw - 1) / q.ycw;
   q.mu = p.mu;
@@ -374,7 +363,7 @@ static tctf_status ctx_init(tctf_ctx* c, const tctf_params* prm, const float* G,
   const Plan& p = c->plan;
   tctf::slice_set_attr(p.n3, tctf::slice_launch_lds_bytes(p));
   tctf::ystep_set_attr(tctf::ystep_lds_bytes(p.r, p.ycw));
-  tctf::bgemm_set_attr(tctf::bgemm_lds_bytes(p.r, p.chunk));
+  tctf::bgemm_set_attr();
   tctf::gramx_set_attr(p.r);
   tctf::pinvy_set_attr(p.r);
   tctf::zgemm_set_attr(p.r);
@@ -465,8 +454,8 @@ static tctf_status time_iterations(tctf_ctx* c, int warm, int reps, float* ms) {
   return TCTF_OK;
 }
 
-// Coordinate search from the default shape: each slice path the sizes allow, then the chunk
-// rows, then the Y-step columns; every trial times a few iterations, after which the
+// Coordinate search from the default shape: each slice path the sizes allow, then the
+// columns per X~^* W~ block, then the Y-step columns; every trial times a few iterations, after which the
 // initial iterate is built again.  The context ends at its initial iterate with the best
 // shape.
 static tctf_status autotune(tctf_ctx* c, const tctf_params* prm, const float* G, const uint8_t* omega,
@@ -497,12 +486,12 @@ static tctf_status autotune(tctf_ctx* c, const tctf_params* prm, const float* G,
     }
   };
   for (int path : {tctf::SPATH_COOP, tctf::SPATH_THREAD, tctf::SPATH_SPLIT})
-    if (path != best.spath && tctf::slice_path_valid(path, prm->n2, prm->n3)) trial({path, best.chunk, best.ycw});
-  for (int chunk : {16, 32, 48, 64})
-    if (chunk != best.chunk && chunk >= TUNE_MIN_CHUNK) trial({best.spath, chunk, best.ycw});
+    if (path != best.spath && tctf::slice_path_valid(path, prm->n2, prm->n3)) trial({path, best.bcg, best.ycw});
+  for (int bcg : {16, 32})
+    if (bcg != best.bcg && tctf::bgemm_cols_valid(prm->r, bcg)) trial({best.spath, bcg, best.ycw});
   const int ymax = 512 / prm->r < prm->n2 ? 512 / prm->r : prm->n2;   // the Y-step block holds r x ycw <= 512
   for (int ycw : {8, 16, 32, 64, ymax})
-    if (ycw != best.ycw && ycw >= TUNE_MIN_YCW && ycw <= ymax) trial({best.spath, best.chunk, ycw});
+    if (ycw != best.ycw && ycw >= TUNE_MIN_YCW && ycw <= ymax) trial({best.spath, best.bcg, ycw});
   if (s != TCTF_OK) return s;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -514,7 +503,7 @@ static tctf_status autotune(tctf_ctx* c, const tctf_params* prm, const float* G,
 tctf_status tctf_tuning(tctf_ctx* c, int32_t out[4]) {
   if (!c || !out) return fail(TCTF_E_ARG, "NULL argument");
   out[0] = c->knobs.spath;
-  out[1] = c->knobs.chunk;
+  out[1] = c->knobs.bcg;
   out[2] = c->knobs.ycw;
   out[3] = c->tuned_from_cache;
   return TCTF_OK;

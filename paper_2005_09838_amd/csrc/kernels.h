@@ -9,7 +9,7 @@ namespace tctf {
 // Device buffers and sizes of one completion (carved from the caller's workspace).
 struct Plan {
   int n1, n2, n3, r, nb;       // nb = n3/2 + 1 stored frequencies
-  int nchunk, chunk;           // row chunks of the X~^* W~ reduction
+  int bcg;                     // complex columns per X~^* W~ block (16 or 32)
   int ny, ycw;                 // column blocks of the Y-step per frequency, columns per block
   int spath;                   // slice path: SPATH_COOP, SPATH_THREAD or SPATH_SPLIT
   double mu, rho1, rho2, eta;
@@ -22,7 +22,7 @@ struct Plan {
   float2* xt;       // X~ [nb][r][n1]
   float2* yt;       // Y~ [nb][r][n2]
   float2* rhs;      // right-hand side of the H_rho1 solve [nb][r][n1]
-  double2* bpart;   // partial X~^* W~ [nb][nchunk][r][n2] (FP64)
+  double2* bpart;   // X~^* W~ [nb][r][n2] (FP64)
   cd* gxpart;       // partial Grams of X~ over row groups [nb][ngroup][2][r][r] (FP64)
   cd* gxm;          // G_X = X~^* H_rho1 X~ [nb][r][r]
   cd* dmat;         // (H X~)^* (H X~) [nb][r][r]
@@ -87,13 +87,14 @@ void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_fro
 void launch_zgemm(const Plan& p, int with_pinv = 0);   // with_pinv: also G_Y^+ (pinvy_block)
 void launch_agemm(const Plan& p, int raw_a = 0, int advance = 0);   // advance: next rounding-bit counter
 void launch_hsolve(const Plan& p);
-void launch_bgemm(const Plan& p);   // X~^* W~ chunk partials
+void launch_bgemm(const Plan& p);   // X~^* W~ over all rows
 void launch_gramx(const Plan& p);   // G_X, (H X~)^*(H X~), G_X^+ and I - eta P_X
 int gramx_groups(int n1);
 void gramx_set_attr(int r);
-size_t bgemm_lds_bytes(int r, int chunk);
+size_t bgemm_lds_bytes(int r, int bcg);
+bool bgemm_cols_valid(int r, int bcg);
 
-void bgemm_set_attr(size_t lds);
+void bgemm_set_attr();
 void launch_ystep(const Plan& p, int init);
 void ystep_split(int n2, int r, int nb, int* ny, int* cw);
 size_t ystep_lds_bytes(int r, int cw);

@@ -13,7 +13,7 @@ __global__ void __launch_bounds__(256) k_stat_bin(const float2* __restrict__ xt,
                                                   const void* __restrict__ wt, const float2* __restrict__ a,
                                                   const double2* __restrict__ bpart, const cd* __restrict__ gxm,
                                                   double* __restrict__ out, int n1, int n2, int n3, int r,
-                                                  int nb, int nchunk, double rho1, int mixed) {
+                                                  int nb, double rho1, int mixed) {
   __shared__ cd gy[TCTF_RMAX * TCTF_RMAX];
   __shared__ cd gx[TCTF_RMAX * TCTF_RMAX];
   __shared__ double red[16];
@@ -39,11 +39,9 @@ __global__ void __launch_bounds__(256) k_stat_bin(const float2* __restrict__ xt,
       const float2 y = Y[(size_t)t * n2 + j];
       cd_fma(v, gx[s * r + t], cd_make(y.x, y.y));
     }
-    for (int c = 0; c < nchunk; ++c) {
-      const double2 bb = bpart[(((size_t)b * nchunk + c) * r + s) * n2 + j];
-      v.re -= bb.x;
-      v.im -= bb.y;
-    }
+    const double2 bb = bpart[((size_t)b * r + s) * n2 + j];
+    v.re -= bb.x;
+    v.im -= bb.y;
     gyn += v.re * v.re + v.im * v.im;
     const float2 y = Y[(size_t)s * n2 + j];
     yn += (double)y.x * y.x + (double)y.y * y.y;
@@ -120,9 +118,9 @@ __global__ void k_stat_final(const double* __restrict__ part, int nb, const doub
 void launch_stationarity(const Plan& p, int w_from_g) {
   launch_agemm(p, 1);   // A = W~ Y~^* into the right-hand-side buffer
   launch_gramx(p);      // G_X
-  launch_bgemm(p);      // X~^* W~ partial sums
+  launch_bgemm(p);      // X~^* W~
   k_stat_bin<<<p.nb, 256, 0, p.stream>>>(p.xt, p.yt, p.wt, p.rhs, p.bpart, p.gxm, p.stat_work, p.n1,
-                                         p.n2, p.n3, p.r, p.nb, p.nchunk, p.rho1, p.mixed);
+                                         p.n2, p.n3, p.r, p.nb, p.rho1, p.mixed);
   launch_zgemm(p);
   launch_slice(p, SLICE_KKT, nullptr, nullptr, w_from_g);
   k_stat_final<<<1, 256, 0, p.stream>>>(p.stat_work, p.nb, p.kkt, p.n1, p.scal + 8);

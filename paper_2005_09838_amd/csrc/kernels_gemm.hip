@@ -458,7 +458,11 @@ __global__ void __launch_bounds__(256) k_gramx_part(const float2* __restrict__ x
   }
 }
 
+#define GXI_B 12   // row-group partials loaded at once
 __global__ void __launch_bounds__(256) k_gramx_inv(const cd* __restrict__ part, int ngrp, int r, GramOut go) {
+  // this small launch runs beside the X~^* W~ product on the same compute units: its
+  // wavefronts take issue priority there, since the Y-step waits for the later of the two
+  __builtin_amdgcn_s_setprio(3);
   extern __shared__ __align__(16) unsigned char sm[];
   const int b = blockIdx.x, tid = threadIdx.x, rr = r * r;
   cd* gx = (cd*)sm;
@@ -472,10 +476,22 @@ __global__ void __launch_bounds__(256) k_gramx_inv(const cd* __restrict__ part, 
   ps.red = ps.rot + 96;
   for (int e = tid; e < rr; e += 256) {
     cd sv = cd_make(0.0, 0.0), dv = cd_make(0.0, 0.0);
-    for (int g = 0; g < ngrp; ++g) {   // fixed order
-      const cd* pg = part + (size_t)(b * ngrp + g) * 2 * rr;
-      sv = cd_add(sv, pg[e]);
-      dv = cd_add(dv, pg[rr + e]);
+    const cd* pb = part + (size_t)b * ngrp * 2 * rr + e;
+    for (int g0 = 0; g0 < ngrp; g0 += GXI_B) {   // GXI_B groups' loads in flight, summed in group order
+      cd vs[GXI_B], vd[GXI_B];
+#pragma unroll
+      for (int k = 0; k < GXI_B; ++k) {
+        const bool ok = g0 + k < ngrp;
+        vs[k] = ld_or(pb, (size_t)(g0 + k) * 2 * rr, ok, cd_make(0.0, 0.0));
+        vd[k] = ld_or(pb, (size_t)(g0 + k) * 2 * rr + rr, ok, cd_make(0.0, 0.0));
+      }
+#pragma unroll
+      for (int k = 0; k < GXI_B; ++k) {
+        if (g0 + k < ngrp) {
+          sv = cd_add(sv, vs[k]);
+          dv = cd_add(dv, vd[k]);
+        }
+      }
     }
     const cd gv = cd_add(sv, cd_scale(dv, go.rho1));
     go.gxm[(size_t)b * rr + e] = gv;
@@ -524,146 +540,171 @@ void launch_gramx(const Plan& p) {
 }
 
 // ---------------------------------------------------------------- X~^* W~
-// Real form: C'[2s + d][2j + c] = sum_i X'[2s + d][i] W'[i][2j + c] with X'[2s + d][i] =
-// (re, im)_d X~(i, s) and W' the interleaved W~ rows; then
-// (X~^* W~)(s, j) = (C'[2s][2j] + C'[2s+1][2j+1], C'[2s][2j+1] - C'[2s+1][2j]).
-// Block: one chunk of at most 64 rows x one frequency.  The chunk's X~ rows and, per pass
-// of BG_COLS columns, its whole W~ slab are staged in LDS with every load of a thread
-// issued at once; each wavefront owns a quarter of the 16-column tiles of a pass, on the
-// FP64 matrix cores.
-#define BG_COLS 64                  // complex columns per pass
-#define BG_MAXROWS 64               // rows per chunk at most
-#define BG_WLD (2 * BG_COLS + 16)   // LDS row stride of the staged W~ slab (floats)
-template <int RM>   // r <= RM
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RM <= 16 ? 2 : 1)))
-k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt, double2* __restrict__ bpart, int n1,
-        int n2, int r, int nb, int nchunk, int chunk, int mixed) {
-  extern __shared__ __align__(16) float smb[];
-  const int xld = 2 * r + 16;                    // LDS row stride of the staged X~ rows (floats)
-  float* xs = smb;                               // [chunk + 1][xld]: (re, im) of X~(i, s) at 2 s
-  float* ws = smb + (size_t)(chunk + 1) * xld;   // [chunk rounded up to 4][BG_WLD]
-  const int c = (int)blockIdx.x % nchunk, b = (int)blockIdx.x / nchunk, tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
-  const int i0 = c * chunk, i1 = min(n1, i0 + chunk), nrows = i1 - i0;
-  const int rows = nrows;
-  const int nks = (nrows + 3) / 4;   // K steps of 4 rows
-  // W~ slab of one pass: rows i0 .. i1 - 1 (zeros up to a multiple of 4), columns
-  // j0 .. j0 + nc - 1; 16 elements per thread, loaded into registers ahead of their use
-  constexpr int SLAB_PER = BG_MAXROWS * BG_COLS / 256;
-  float2 slab[SLAB_PER];
-  auto load_slab = [&](int j0) {
-    const int nc = min(BG_COLS, n2 - j0);
-    // (the storage branch outside the unrolled loops, so that no load waits at a join)
-    if (mixed) {
+// Real form with the real and imaginary parts in separate tiles: X''[p RM + s][i] =
+// (re, im)_p X~(i, s) and W''[i][p CW + c] = (re, im)_p W~(i, j0 + c), C = X''^T W'', so
+// (X~^* W~)(s, j0 + c) = (C[s][c] + C[RM + s][CW + c], C[s][CW + c] - C[RM + s][c]) and the
+// four terms of one output sit in the same lane and element of four tiles.  Each lane loads
+// X~(i, s) and W~(i, j) once per K step and feeds both parts to the FP64 matrix cores.
+// Block: one frequency b and CW = 16 WL complex columns, reduced over every row i in the
+// block: its BG_W wavefronts take contiguous ranges of 4-row K steps (XL = RM / 16 row
+// tiles and WL column tiles of each part), with two groups of loads in flight.  X~ and W~
+// are FP32 or BF16 values, exact in FP64, so the sums carry FP64 rounding only (the Y-step's
+// G_X^+ amplifies any rounding of X~^* W~).  The wavefronts' complex results are added in a
+// fixed tree order through LDS, so the result does not depend on timing.  Block order: the
+// column groups of one frequency run on one XCD (blocks are dealt to the eight XCDs in
+// turn), so each XCD's L2 holds the X~ rows of its own frequencies only.
+#define BG_W 8    // wavefronts per block
+template <int XL, int WL>
+struct BgShape {
+  static constexpr int KG = 16 / (XL + WL);   // K steps per load group (two groups in flight)
+};
+template <int XL, int WL, bool MX>
+__device__ __forceinline__ void bg_load(const void* __restrict__ wt, const float2* __restrict__ xt, int ks, int ks1,
+                                        int q, int m, int b, int r, int n1, int n2, int nb, int j0,
+                                        float2 (&xv)[BgShape<XL, WL>::KG][XL], float2 (&wv)[BgShape<XL, WL>::KG][WL]) {
+  constexpr int KG = BgShape<XL, WL>::KG;
 #pragma unroll
-      for (int u = 0; u < SLAB_PER; ++u) {
-        const int e = tid + 256 * u, rr = e / BG_COLS, jj = e % BG_COLS;
-        const size_t idx = ((size_t)(i0 + rr) * nb + b) * n2 + j0 + jj;
-        slab[u] = unpack_bf16x2(ld_or((const uint32_t*)wt, idx, rr < nrows && jj < nc, 0u));
-      }
-    } else {
+  for (int k = 0; k < KG; ++k) {
+    const int i = 4 * (ks + k) + q;
+    const bool rowok = ks + k < ks1 && i < n1;
 #pragma unroll
-      for (int u = 0; u < SLAB_PER; ++u) {
-        const int e = tid + 256 * u, rr = e / BG_COLS, jj = e % BG_COLS;
-        const size_t idx = ((size_t)(i0 + rr) * nb + b) * n2 + j0 + jj;
-        slab[u] = ld_or((const float2*)wt, idx, rr < nrows && jj < nc, make_float2(0.f, 0.f));
+    for (int a = 0; a < XL; ++a) {
+      const int s = 16 * a + m;
+      xv[k][a] = ld_or(xt, ((size_t)b * r + s) * n1 + i, rowok && s < r, make_float2(0.f, 0.f));
+    }
+#pragma unroll
+    for (int u = 0; u < WL; ++u) {
+      const int j = j0 + 16 * u + m;
+      const size_t idx = ((size_t)i * nb + b) * n2 + j;
+      if constexpr (MX) wv[k][u] = unpack_bf16x2(ld_or((const uint32_t*)wt, idx, rowok && j < n2, 0u));
+      else wv[k][u] = ld_or((const float2*)wt, idx, rowok && j < n2, make_float2(0.f, 0.f));
+    }
+  }
+}
+
+template <int XL, int WL>
+__device__ __forceinline__ void bg_mfma(const float2 (&xv)[BgShape<XL, WL>::KG][XL],
+                                        const float2 (&wv)[BgShape<XL, WL>::KG][WL], int cnt,
+                                        v4d (&acc)[2 * XL][2 * WL]) {
+  constexpr int KG = BgShape<XL, WL>::KG;
+#pragma unroll
+  for (int k = 0; k < KG; ++k) {
+    if (k < cnt) {   // the same in the whole wavefront
+#pragma unroll
+      for (int a = 0; a < 2 * XL; ++a) {
+        const double av = (double)(a < XL ? xv[k][a].x : xv[k][a - XL].y);
+#pragma unroll
+        for (int u = 0; u < 2 * WL; ++u) {
+          const double bv = (double)(u < WL ? wv[k][u].x : wv[k][u - WL].y);
+          acc[a][u] = mfma4d(av, bv, acc[a][u]);
+        }
       }
     }
-  };
-  load_slab(0);
-  stage_batched_to<8, float2>(rows * r, [&](int e) {
-    const int s = e / rows, h = e % rows;
-    return xt[((size_t)b * r + s) * n1 + i0 + h];
-  }, [&](int e, float2 v) {
-    const int s = e / rows, h = e % rows;
-    xs[h * xld + 2 * s] = v.x;
-    xs[h * xld + 2 * s + 1] = v.y;
-  });
-  constexpr int MT = RM / 8;               // 16-row tiles of X' (2 RM rows)
-  for (int j0 = 0; j0 < n2; j0 += BG_COLS) {
-    const int nc = min(BG_COLS, n2 - j0);
-    const int ntiles = (2 * nc + 15) / 16;   // at most 8; wavefront w takes tiles w and w + 4
-    __syncthreads();   // the previous pass is done with the slab in LDS
+  }
+}
+
+template <int XL, int WL, bool MX>   // r <= 16 XL, 16 WL complex columns per block, MX: W~ in BF16
+__global__ void __launch_bounds__(64 * BG_W) __attribute__((amdgpu_waves_per_eu(XL + WL <= 2 ? 4 : 2))) k_bgemm(const void* __restrict__ wt, const float2* __restrict__ xt,
+                                                      double2* __restrict__ bout, int n1, int n2, int r, int nb,
+                                                      int ncg) {
+  constexpr int KG = BgShape<XL, WL>::KG;
+  extern __shared__ __align__(16) double2 bred[];   // [BG_W / 2][XL][WL][4][64]
+  // XCD-aware order: block id -> (frequency, column group)
+  const int nblk = (int)gridDim.x, id = (int)blockIdx.x, x = id & 7, qd = nblk >> 3, rem = nblk & 7;
+  const int lid = x * qd + min(x, rem) + (id >> 3);
+  const int b = lid / ncg, cg = lid % ncg, j0 = 16 * WL * cg;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
+  const int nks = (n1 + 3) >> 2, per = (nks + BG_W - 1) / BG_W;
+  const int ks0 = min(nks, w * per), ks1 = min(nks, ks0 + per);
+  v4d acc[2 * XL][2 * WL];
 #pragma unroll
-    for (int u = 0; u < SLAB_PER; ++u) {
-      const int e = tid + 256 * u, rr = e / BG_COLS, jj = e % BG_COLS;
-      if (rr < 4 * nks) *(float2*)&ws[rr * BG_WLD + 2 * jj] = slab[u];
+  for (int a = 0; a < 2 * XL; ++a)
+#pragma unroll
+    for (int u = 0; u < 2 * WL; ++u) acc[a][u] = v4d{0.0, 0.0, 0.0, 0.0};
+  float2 xa[KG][XL], wa[KG][WL], xb[KG][XL], wb[KG][WL];
+  bg_load<XL, WL, MX>(wt, xt, ks0, ks1, q, m, b, r, n1, n2, nb, j0, xa, wa);
+  for (int ks = ks0; ks < ks1; ks += 2 * KG) {
+    if (ks + KG < ks1) bg_load<XL, WL, MX>(wt, xt, ks + KG, ks1, q, m, b, r, n1, n2, nb, j0, xb, wb);
+    bg_mfma<XL, WL>(xa, wa, ks1 - ks, acc);
+    if (ks + KG >= ks1) break;
+    if (ks + 2 * KG < ks1) bg_load<XL, WL, MX>(wt, xt, ks + 2 * KG, ks1, q, m, b, r, n1, n2, nb, j0, xa, wa);
+    bg_mfma<XL, WL>(xb, wb, ks1 - ks - KG, acc);
+  }
+  // complex results of this wavefront: element t of lane (q, m) is row q + 4 t, column m of
+  // each tile, i.e. s = 16 a + q + 4 t, j = j0 + 16 u + m
+  double2 cz[XL][WL][4];
+#pragma unroll
+  for (int a = 0; a < XL; ++a)
+#pragma unroll
+    for (int u = 0; u < WL; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        cz[a][u][t] = make_double2(acc[a][u][t] + acc[XL + a][WL + u][t], acc[a][WL + u][t] - acc[XL + a][u][t]);
+  // fixed-order tree over the wavefronts: w += w + h for h = BG_W / 2, ..., 1
+#pragma unroll
+  for (int h = BG_W / 2; h >= 1; h >>= 1) {
+    if (w >= h && w < 2 * h) {
+#pragma unroll
+      for (int a = 0; a < XL; ++a)
+#pragma unroll
+        for (int u = 0; u < WL; ++u)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) bred[((((w - h) * XL + a) * WL + u) * 4 + t) * 64 + lane] = cz[a][u][t];
     }
     __syncthreads();
-    if (j0 + BG_COLS < n2) load_slab(j0 + BG_COLS);   // the next pass's slab, in flight meanwhile
-    // FP64 matrix-core tiles over every row of the chunk: X~ and W~ are FP32 (or BF16)
-    // values, exact in FP64, so the partial sums carry FP64 rounding only (the Y-step's
-    // G_X^{-1} amplifies any rounding of X~^* W~)
-    v4d acc[MT][2];
+    if (w < h) {
 #pragma unroll
-    for (int a = 0; a < MT; ++a)
+      for (int a = 0; a < XL; ++a)
 #pragma unroll
-      for (int u = 0; u < 2; ++u) acc[a][u] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int ks = 0; ks < nks; ++ks) {
-      const int kr = 4 * ks + q;   // chunk row of this lane's K index
-      double av[MT];
-#pragma unroll
-      for (int a = 0; a < MT; ++a) {
-        const int sp = 16 * a + m;   // row 2 s + d of X'
-        av[a] = (sp < 2 * r && kr < nrows) ? (double)xs[kr * xld + sp] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int nt = w + 4 * u;
-        if (nt < ntiles) {
-          const double bv = (double)ws[kr * BG_WLD + 16 * nt + m];
-#pragma unroll
-          for (int a = 0; a < MT; ++a) acc[a][u] = mfma4d(av[a], bv, acc[a][u]);
-        }
-      }
-    }
-    // combine C' into (X~^* W~)(s, j): element t of lane (q, m) holds row 16 a + q + 4 t and
-    // column 16 nt + m of its tile, so the lanes with q and m even hold C'[2s][2j] and read
-    // C'[2s][2j+1], C'[2s+1][2j] and C'[2s+1][2j+1] from lanes + 1, + 16 and + 17
-#pragma unroll
-    for (int a = 0; a < MT; ++a) {
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int nt = w + 4 * u;   // the same in the whole wavefront
-        if (nt < ntiles) {
-          const int j = (16 * nt + m) >> 1;
+        for (int u = 0; u < WL; ++u)
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            const double s0 = acc[a][u][t], s1 = __shfl_down(s0, 1), s16 = __shfl_down(s0, 16),
-                         s17 = __shfl_down(s0, 17);
-            const int s = (16 * a + q + 4 * t) >> 1;
-            if (!(q & 1) && !(m & 1) && s < r && j < nc)
-              bpart[(((size_t)b * nchunk + c) * r + s) * n2 + j0 + j] = make_double2(s0 + s17, s1 - s16);
+            const double2 o = bred[(((w * XL + a) * WL + u) * 4 + t) * 64 + lane];
+            cz[a][u][t].x += o.x;
+            cz[a][u][t].y += o.y;
           }
-        }
-      }
     }
+    __syncthreads();
   }
+  if (w != 0) return;
+#pragma unroll
+  for (int a = 0; a < XL; ++a)
+#pragma unroll
+    for (int u = 0; u < WL; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int s = 16 * a + q + 4 * t, j = j0 + 16 * u + m;
+        if (s < r && j < n2) bout[((size_t)b * r + s) * n2 + j] = cz[a][u][t];
+      }
 }
 
-size_t bgemm_lds_bytes(int r, int chunk) {
-  const size_t slab = (size_t)((chunk + 3) / 4 * 4) * BG_WLD * sizeof(float);
-  return (size_t)(chunk + 1) * (2 * r + 16) * sizeof(float) + slab;
+size_t bgemm_lds_bytes(int r, int bcg) {
+  const int xl = r <= 16 ? 1 : 2, wl = bcg / 16;
+  return (size_t)(BG_W / 2) * xl * wl * 4 * 64 * sizeof(double2);
 }
 
-void bgemm_set_attr(size_t lds) {
-  if (lds > 65536) {
-    (void)hipFuncSetAttribute((const void*)k_bgemm<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)k_bgemm<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)k_bgemm<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  }
-}
+bool bgemm_cols_valid(int r, int bcg) { return (bcg == 16 || bcg == 32) && r <= 32; }
 
-// X~^* W~ chunk partials only (G_X: launch_gramx).
+void bgemm_set_attr() {}   // at most 64 KB of LDS per block
+
+// X~^* W~ -> bpart [nb][r][n2] (G_X: launch_gramx).
 void launch_bgemm(const Plan& p) {
-  const int grid = p.nchunk * p.nb;   // (chunk, frequency)
-  const size_t lds = bgemm_lds_bytes(p.r, p.chunk);
-#define TCTF_BGEMM(RM)                                                                                  \
-  k_bgemm<RM><<<grid, 256, lds, p.stream>>>(p.wt, p.xt, p.bpart, p.n1, p.n2, p.r, p.nb, p.nchunk, p.chunk, \
-                                            p.mixed)
-  if (p.r <= 8) TCTF_BGEMM(8);
-  else if (p.r <= 16) TCTF_BGEMM(16);
-  else TCTF_BGEMM(32);
+  const int ncg = (p.n2 + p.bcg - 1) / p.bcg;
+  const int grid = ncg * p.nb;
+  const size_t lds = bgemm_lds_bytes(p.r, p.bcg);
+#define TCTF_BGEMM(XL, WL)                                                                                       \
+  do {                                                                                                           \
+    if (p.mixed) k_bgemm<XL, WL, true><<<grid, 64 * BG_W, lds, p.stream>>>(p.wt, p.xt, p.bpart, p.n1, p.n2, p.r, p.nb, ncg);  \
+    else k_bgemm<XL, WL, false><<<grid, 64 * BG_W, lds, p.stream>>>(p.wt, p.xt, p.bpart, p.n1, p.n2, p.r, p.nb, ncg); \
+  } while (0)
+  const bool wide = p.bcg == 32;
+  if (p.r <= 16) {
+    if (wide) TCTF_BGEMM(1, 2);
+    else TCTF_BGEMM(1, 1);
+  } else {
+    if (wide) TCTF_BGEMM(2, 2);
+    else TCTF_BGEMM(2, 1);
+  }
 #undef TCTF_BGEMM
 }
 

@@ -322,6 +322,41 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
 
 
 
+// Value of lane - d (up) or lane + d (down) within the S-lane group of a row.  For S <= 16
+// the group lies in one 16-lane DPP row and the move is a row shift of the VALU (lanes whose
+// source falls outside the row read 0; callers only use lanes whose source is in the group);
+// wider groups go through the LDS crossbar.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int S>
+__device__ __forceinline__ float seg_up(float v, int d) {
+  if constexpr (S <= 16) {
+    switch (d) {
+      case 1: return dpp_mov<0x111>(v);   // row_shr:1
+      case 2: return dpp_mov<0x112>(v);
+      case 4: return dpp_mov<0x114>(v);
+      default: return dpp_mov<0x118>(v);
+    }
+  } else {
+    return __shfl_up(v, d, S);
+  }
+}
+template <int S>
+__device__ __forceinline__ float seg_down(float v, int d) {
+  if constexpr (S <= 16) {
+    switch (d) {
+      case 1: return dpp_mov<0x101>(v);   // row_shl:1
+      case 2: return dpp_mov<0x102>(v);
+      case 4: return dpp_mov<0x104>(v);
+      default: return dpp_mov<0x108>(v);
+    }
+  } else {
+    return __shfl_down(v, d, S);
+  }
+}
+
 // W-step of every row (i, :, k) with S threads per row: thread (k, s) takes columns
 // [s L, (s+1) L).  Both Thomas passes are first-order affine recurrences,
 //   forward  y_j = a_j y_{j-1} + b_j  (a = rho2 / alpha_j, b = v_j / alpha_j; a = 0, b = g_j observed)
@@ -329,9 +364,15 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
 // so each thread composes its segment's map, the S maps of a row are combined by a
 // scan across the S lanes, and each thread then runs its segment once more from the
 // right boundary value.  S divides 64 and is a power of two; L <= LMAX.
-template <int LMAX, int S>
+// OBJ: also the row's terms of f0 from the solved values still in registers (the
+// neighbours across segment ends from the adjacent lanes): ridge sum w_j^2, K term
+// sum (w_{j+1} - w_j)^2 and, on unobserved entries, the fit residual z_j - w_j, which the
+// row's equation gives as (mu + rho2 deg_j) w_j - rho2 (w_{j-1} + w_{j+1}); added to fr, fs,
+// ff.
+template <int LMAX, int S, bool OBJ>
 __device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* tab, const uint32_t* obits, int nwr,
-                                                int n2, int N, float rho2) {
+                                                int n2, int N, float rho2, float mu, float& fr, float& fs,
+                                                float& ff) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int L = (n2 + S - 1) / S;
   for (int kk = tid; kk < N * S; kk += nt) {
@@ -350,6 +391,7 @@ __device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* 
       pos = ja - last - 1;
     }
     float av[LMAX], bv[LMAX], cv[LMAX];
+    uint32_t obm = 0u;   // bit u: entry ja + u is observed
     float A = 1.0f, B = 0.0f;
 #pragma unroll
     for (int u = 0; u < LMAX; ++u) {
@@ -362,6 +404,7 @@ __device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* 
         av[u] = o ? 0.0f : rho2 * invf;
         bv[u] = o ? v : v * invf;
         cv[u] = (o || j == n2 - 1) ? 0.0f : rho2 * invb;
+        obm |= (uint32_t)o << u;
         seen |= o;
         pos = o ? 0 : pos + 1;
         B = fmaf(av[u], B, bv[u]);
@@ -369,11 +412,12 @@ __device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* 
       }
     }
     // forward: combine the segment maps of the row (lanes k*S .. k*S+S-1)
+#pragma unroll
     for (int d = 1; d < S; d <<= 1) {
-      const float a2 = __shfl_up(A, d, S), b2 = __shfl_up(B, d, S);
+      const float a2 = seg_up<S>(A, d), b2 = seg_up<S>(B, d);
       if (s >= d) { B = fmaf(A, b2, B); A *= a2; }
     }
-    float y = __shfl_up(B, 1, S);
+    float y = seg_up<S>(B, 1);
     if (s == 0) y = 0.0f;
     float C = 1.0f, D = 0.0f;
 #pragma unroll
@@ -390,18 +434,47 @@ __device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* 
         C *= cv[u];
       }
     }
+#pragma unroll
     for (int d = 1; d < S; d <<= 1) {
-      const float c2 = __shfl_down(C, d, S), d2 = __shfl_down(D, d, S);
+      const float c2 = seg_down<S>(C, d), d2 = seg_down<S>(D, d);
       if (s + d < S) { D = fmaf(C, d2, D); C *= c2; }
     }
-    float w = __shfl_down(D, 1, S);
+    float w = seg_down<S>(D, 1);
     if (s == S - 1) w = 0.0f;
 #pragma unroll
     for (int u = LMAX - 1; u >= 0; --u) {
       const int j = ja + u;
       if (j < jb) {
         w = fmaf(cv[u], w, bv[u]);
+        bv[u] = w;   // w_j
         zs[j * LD + k] = w;
+      }
+    }
+    if constexpr (OBJ) {
+      // the segments before the last non-empty one are full, so lane s - 1's last value is
+      // w_{ja - 1} and lane s + 1's first value is w_{jb} wherever they exist
+      float last = 0.0f;
+#pragma unroll
+      for (int u = 0; u < LMAX; ++u)
+        if (ja + u < jb) last = bv[u];
+      const float left = seg_up<S>(last, 1), right = seg_down<S>(bv[0], 1);
+      float wl = left;
+#pragma unroll
+      for (int u = 0; u < LMAX; ++u) {
+        const int j = ja + u;
+        if (j < jb) {
+          const float wq = bv[u];
+          const float wr = (u + 1 < LMAX && j + 1 < jb) ? bv[u + 1 < LMAX ? u + 1 : u] : right;
+          const bool has_l = j > 0, has_r = j + 1 < n2;
+          const float l = has_l ? wl : 0.0f, r = has_r ? wr : 0.0f;
+          const float cj = fmaf(rho2, (has_l ? 1.0f : 0.0f) + (has_r ? 1.0f : 0.0f), mu);
+          const float d = ((obm >> u) & 1u) ? 0.0f : fmaf(cj, wq, -rho2 * (l + r));
+          const float dr = has_r ? r - wq : 0.0f;
+          fr = fmaf(wq, wq, fr);
+          fs = fmaf(dr, dr, fs);
+          ff = fmaf(d, d, ff);
+          wl = wq;
+        }
       }
     }
   }
@@ -515,25 +588,36 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
   __syncthreads();
 
   // ---- 2. W-step along mode 2 for the rows (i, :, k), S threads per row
+  // in an iteration the f0 terms of the solved rows come from the W-step's registers
+  constexpr bool OBJ = MODE == SLICE_ITER;
+  float wfr = 0.0f, wfs = 0.0f, wff = 0.0f;
   if (thomas) {
     int S = 1;
     while (S < 64 && 2 * S * N <= nt) S <<= 1;
     while ((n2 + S - 1) / S > COOP_WS_L) S <<= 1;   // segment length within the register budget
+    const float muf = (float)a.mu;
     switch (S) {   // the segment count is a compile-time constant of the shuffles
-      case 1: wstep_segmented<COOP_WS_L, 1>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      case 2: wstep_segmented<COOP_WS_L, 2>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      case 4: wstep_segmented<COOP_WS_L, 4>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      case 8: wstep_segmented<COOP_WS_L, 8>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      case 16: wstep_segmented<COOP_WS_L, 16>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      case 32: wstep_segmented<COOP_WS_L, 32>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
-      default: wstep_segmented<COOP_WS_L, 64>(zs, LD, tab, obits, nwr, n2, N, a.rho2); break;
+#define TCTF_WSTEP(SS) \
+  case SS: wstep_segmented<COOP_WS_L, SS, OBJ>(zs, LD, tab, obits, nwr, n2, N, a.rho2, muf, wfr, wfs, wff); break;
+      TCTF_WSTEP(1)
+      TCTF_WSTEP(2)
+      TCTF_WSTEP(4)
+      TCTF_WSTEP(8)
+      TCTF_WSTEP(16)
+      TCTF_WSTEP(32)
+#undef TCTF_WSTEP
+      default: wstep_segmented<COOP_WS_L, 64, OBJ>(zs, LD, tab, obits, nwr, n2, N, a.rho2, muf, wfr, wfs, wff); break;
     }
   }
   __syncthreads();
 
   if (MODE == SLICE_KKT) fit = ridge = sm = 0.0;   // phase 3 takes maxima instead of sums
-  // ---- 3. remaining objective terms (see k_slice), then the forward transform
-  if (act) {
+  ridge += (double)wfr;
+  sm += (double)wfs;
+  fit += (double)wff;
+  // ---- 3. remaining objective terms (see k_slice; in an iteration the W-step gave them),
+  // then the forward transform
+  if (act && !(OBJ && thomas)) {
     const bool has_l = j > 0, has_r = j + 1 < n2;
     const int jw = j >> 5;
     const uint32_t jb = 1u << (j & 31);

@@ -203,19 +203,16 @@ void ystep_split(int n2, int r, int nb, int* ny, int* cw) {
 }
 
 // Block (column block jb, frequency b), 256 threads, r <= RM; G_X^+ and I - eta P_X come
-// from the X~^* W~ launch (gramx_block).  Every load of the block is issued before any use:
-// G_X^+ and q, the old columns and the chunk partials of X~^* W~ for the block's columns
-// (YS_CP1 in the first batch, summed in a fixed order).  Then Y~ <- (I - eta P_X) Y~ +
-// eta G_X^+ X~^* W~ (eq. (updataXYW1)) is formed on the block's columns in FP64 and stored
-// in FP32, and the block's FP64 partial of G_Y = Y~ Y~^* from the stored values.  init: only
-// the partial of G_Y.
-#define YS_CP1 12   // chunk partials of X~^* W~ in the first batch of loads
-#define YS_CP 8     // and in each later batch
+// from the G_X launch (k_gramx_inv), X~^* W~ from k_bgemm.  Every load of the block is
+// issued before any use: G_X^+ and q, the old columns and X~^* W~ on the block's columns.
+// Then Y~ <- (I - eta P_X) Y~ + eta G_X^+ X~^* W~ (eq. (updataXYW1)) is formed on the
+// block's columns in FP64 and stored in FP32, and the block's FP64 partial of G_Y = Y~ Y~^*
+// from the stored values.  init: only the partial of G_Y.
 template <int RM>
 __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const double2* __restrict__ bpart,
                                                const cd* __restrict__ gxp, const cd* __restrict__ qx,
                                                const int* __restrict__ qx_zero, cd* __restrict__ gyq, int n2,
-                                               int r, int n3, int nchunk, int cw, int ny, double eta, int init) {
+                                               int r, int n3, int cw, int ny, double eta, int init) {
   constexpr int GPT = (RM * RM + 255) / 256;   // r x r entries per thread
   extern __shared__ __align__(16) unsigned char sm[];
   const YLayout L = ystep_layout(r, cw);
@@ -240,43 +237,14 @@ __global__ void __launch_bounds__(256) k_ystep(float2* __restrict__ yt, const do
   }
   const double2 zd = make_double2(0.0, 0.0);
   float2 y[2];
-  double2 v[2][YS_CP1];
-  size_t base[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int e = tid + 256 * u, t = e / nj, jj = e % nj;
-    base[u] = ((size_t)b * nchunk * r + t) * n2 + j0 + jj;
-    y[u] = ld_or(yt, ((size_t)b * r + t) * n2 + j0 + jj, e < nel, z2);
-#pragma unroll
-    for (int k = 0; k < YS_CP1; ++k)
-      v[u][k] = ld_or(bpart, base[u] + (size_t)k * r * n2, !init && e < nel && k < nchunk, zd);
-  }
   cd acc[2];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    acc[u] = zc;
-#pragma unroll
-    for (int k = 0; k < YS_CP1; ++k) {
-      acc[u].re += v[u][k].x;
-      acc[u].im += v[u][k].y;
-    }
-  }
-  if (!init) {
-    for (int c0 = YS_CP1; c0 < nchunk; c0 += YS_CP) {
-      double2 w[2][YS_CP];
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int k = 0; k < YS_CP; ++k)
-          w[u][k] = ld_or(bpart, base[u] + (size_t)(c0 + k) * r * n2, tid + 256 * u < nel && c0 + k < nchunk, zd);
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int k = 0; k < YS_CP; ++k) {
-          acc[u].re += w[u][k].x;
-          acc[u].im += w[u][k].y;
-        }
-    }
+    const int e = tid + 256 * u, t = e / nj, jj = e % nj;
+    const size_t at = ((size_t)b * r + t) * n2 + j0 + jj;
+    y[u] = ld_or(yt, at, e < nel, z2);
+    const double2 v = ld_or(bpart, at, !init && e < nel, zd);
+    acc[u] = cd_make(v.x, v.y);
   }
 #pragma unroll
   for (int k = 0; k < GPT; ++k) {
@@ -362,7 +330,7 @@ void launch_ystep(const Plan& p, int init) {
   const dim3 grid(p.ny, p.nb);
 #define TCTF_YSTEP(RM)                                                                                       \
   k_ystep<RM><<<grid, 256, lds, p.stream>>>(p.yt, p.bpart, p.gxp, p.qx, p.qx_zero, p.gym, p.n2, p.r, p.n3,    \
-                                            p.nchunk, p.ycw, p.ny, p.eta, init)
+                                            p.ycw, p.ny, p.eta, init)
   if (p.r <= 8) TCTF_YSTEP(8);
   else if (p.r <= 16) TCTF_YSTEP(16);
   else TCTF_YSTEP(32);

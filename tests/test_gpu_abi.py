@@ -185,7 +185,7 @@ def test_autotuned_execution_shape(n1, n2, n3, r):
                             autotune=True)
     a = mk()
     ta = a.tuning()
-    assert ta[0] in (1, 2, 3) and ta[1] % 16 == 0 and 16 <= ta[1] <= 64 and ta[2] >= 1
+    assert ta[0] in (1, 2, 3) and ta[1] in (16, 32) and ta[2] >= 1
     a.step(8)
     wa = a.result()["W"].cpu().numpy()
     b = mk()
