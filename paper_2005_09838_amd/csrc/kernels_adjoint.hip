@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(256) k_adj_wstep(const double* __restrict__ wb
     const long i = row / n3, k = row % n3;
     const long base = i * n2 * n3 + k;   // element (i, j, k) at base + j n3
     auto deg = [&](int j) { return n2 == 1 ? 0.0 : ((j == 0 || j == n2 - 1) ? 1.0 : 2.0); };
-    auto unobs = [&](int j) { return is_unobserved(gp[base + (long)j * n3]); };
+    auto unobs = [&](int j) { return is_unobserved(gp[(i * n3 + k) * n2 + j]); };   // packed G: [n1][n3][n2]
     double cprev = 0.0, dprev = 0.0;
     bool uprev = false;
     for (int j = 0; j < n2; ++j) {

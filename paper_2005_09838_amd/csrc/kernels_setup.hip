@@ -9,7 +9,9 @@ size_t wt_elem_bytes(const Plan& p) { return p.mixed ? 4 : 8; }
 // One thread per row (i, k) along mode 2.  Observed entries keep their value (they must
 // be finite); unobserved ones become NaNs carrying their position in the run of
 // consecutive unobserved entries (section 3.3: the equality constraints of the W-step
-// are eliminated row by row, leaving one tridiagonal system per run).
+// are eliminated row by row, leaving one tridiagonal system per run).  The packed copy is
+// stored row by row, [n1][n3][n2]: the slice kernels read entry (i, j, k) for consecutive
+// tubes j at once.
 __global__ void k_pack_g(const float* __restrict__ g, const uint8_t* __restrict__ om,
                          float* __restrict__ gp, int n1, int n2, int n3, int* flag) {
   const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -18,17 +20,17 @@ __global__ void k_pack_g(const float* __restrict__ g, const uint8_t* __restrict_
   int run_start = -1;          // index of the first unobserved entry of the current run
   bool seen_obs = false;
   for (int j = 0; j < n2; ++j) {
-    const long idx = (i * n2 + j) * n3 + k;
+    const long idx = (i * n2 + j) * n3 + k, out = (i * n3 + k) * n2 + j;
     if (om[idx]) {
       const float v = g[idx];
       if (!isfinite(v)) atomicOr(flag, 1);
-      gp[idx] = v;
+      gp[out] = v;
       seen_obs = true;
       run_start = -1;
     } else {
       if (run_start < 0) run_start = j;
       const uint32_t starts_row = seen_obs ? 0u : 1u;
-      gp[idx] = __uint_as_float(pack_unobserved((uint32_t)(j - run_start), starts_row));
+      gp[out] = __uint_as_float(pack_unobserved((uint32_t)(j - run_start), starts_row));
     }
   }
 }

@@ -122,12 +122,12 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
 #pragma unroll
       for (int q = 0; q < N; ++q) dst[q] = z[q];
     }
-    const float* g = gslice + (size_t)j * N;
+    const float* g = gslice + j;   // entry q at g[q n2]
     const int jw0 = (j - lane) >> 5;   // first flag word of this wave's tubes
     float facc = 0.0f;
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-      const float gv = g[q];
+      const float gv = g[(size_t)q * n2];
       const bool obs = !is_unobserved(gv);
       float wv, d;
       if (!thomas) {
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
     const uint32_t jb = 1u << (j & 31);
     if constexpr (MODE == SLICE_KKT) {
       // residuals of eq. (subquKKT): unobserved (W K_{mu rho2} - Z)_ij, observed W - G
-      const float* g = gslice + (size_t)j * N;
+      const float* g = gslice + j;
       float z[N];
       load_inverse_tube<N>(a.zt, i, j, a.nb, n2, z);
 #pragma unroll
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
           const double r = has_r ? (double)wrow[q + LD] : 0.0;
           fit = fmax(fit, fabs((1.0 + cj) * wq - a.rho2d * (l + r) - (double)z[q]));
         } else if (obs) {
-          ridge = fmax(ridge, fabs(wq - (double)g[q]));
+          ridge = fmax(ridge, fabs(wq - (double)g[(size_t)q * n2]));
         }
         sm = fmax(sm, fabs((double)z[q]));
       }
@@ -526,7 +526,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
   const bool act = j < n2;
   const bool thomas = MODE != SLICE_INIT && !a.w_from_g;
   float* row = zs + (size_t)(act ? j : 0) * LD;
-  const float* gtube = a.gp + (i * n2 + (act ? j : 0)) * N;
+  const float* gtube = a.gp + i * n2 * N + (act ? j : 0);   // entry q at gtube[q n2]: a wave reads 64 tubes at once
 
   for (int e = tid; e < 4 * n2; e += nt) tab[e] = a.wtab[e];
   tube_twiddles<N>(twm, twn);
@@ -558,7 +558,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int q = q0 + u * T;
-        gb[u] = ld_or(gtube, (size_t)q, act && q < N, 0.0f);
+        gb[u] = ld_or(gtube, (size_t)q * n2, act && q < N, 0.0f);
       }
 #pragma unroll
       for (int u = 0; u < B; ++u) {
@@ -635,7 +635,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
             const double r = has_r ? (double)row[q + LD] : 0.0;
             fit = fmax(fit, fabs((1.0 + cj) * wq - a.rho2d * (l + r) - (double)z[q]));
           } else if (obs) {
-            ridge = fmax(ridge, fabs(wq - (double)gtube[q]));
+            ridge = fmax(ridge, fabs(wq - (double)gtube[(size_t)q * n2]));
           }
           sm = fmax(sm, fabs((double)z[q]));
         }
