@@ -363,7 +363,7 @@ __device__ __forceinline__ float seg_down(float v, int d) {
 //   backward w_j = c_j w_{j+1} + y_j  (c = rho2 / alpha_j; c = 0 observed or at the last column),
 // so each thread composes its segment's map, the S maps of a row are combined by a
 // scan across the S lanes, and each thread then runs its segment once more from the
-// right boundary value.  S divides 64 and is a power of two; L <= LMAX.
+// right boundary value.  S divides 64 and is a power of two; L <= LMAX <= 32.
 // OBJ: also the row's terms of f0 from the solved values still in registers (the
 // neighbours across segment ends from the adjacent lanes): ridge sum w_j^2, K term
 // sum (w_{j+1} - w_j)^2 and, on unobserved entries, the fit residual z_j - w_j, which the
@@ -379,32 +379,34 @@ __device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* 
     const int k = kk / S, s = kk - k * S;
     const int ja = min(n2, s * L), jb = min(n2, ja + L);
     const uint32_t* ob = obits + k * nwr;
+    // the segment's observed flags (it spans at most two flag words): bit u = entry ja + u
+    const int w0 = ja >> 5;
+    const uint64_t wpair = (uint64_t)ob[min(w0, nwr - 1)] | ((uint64_t)ob[min(w0 + 1, nwr - 1)] << 32);
+    const uint32_t obm = (uint32_t)(wpair >> (ja & 31));
     // run state at ja: position in the current run of unobserved entries, and whether
     // an observed entry precedes it
     int seen, pos;
     {
-      int w = ja >> 5;
-      uint32_t m = ja > 0 ? (ob[w] & ((1u << (ja & 31)) - 1u)) : 0u;
+      int w = w0;
+      uint32_t m = ja > 0 ? ((uint32_t)wpair & ((1u << (ja & 31)) - 1u)) : 0u;
       while (m == 0u && w > 0) m = ob[--w];
       const int last = (m == 0u) ? -1 : (w * 32 + 31 - __clz(m));
       seen = last >= 0;
       pos = ja - last - 1;
     }
     float av[LMAX], bv[LMAX], cv[LMAX];
-    uint32_t obm = 0u;   // bit u: entry ja + u is observed
     float A = 1.0f, B = 0.0f;
 #pragma unroll
     for (int u = 0; u < LMAX; ++u) {
       const int j = ja + u;
       if (j < jb) {
-        const bool o = (ob[j >> 5] >> (j & 31)) & 1u;
+        const bool o = (obm >> u) & 1u;
         const float v = zs[j * LD + k];
         const float invf = tab[o ? 0 : ((j == n2 - 1 ? 2 : 0) + seen) * n2 + pos];
         const float invb = tab[o ? 0 : seen * n2 + pos];
         av[u] = o ? 0.0f : rho2 * invf;
         bv[u] = o ? v : v * invf;
         cv[u] = (o || j == n2 - 1) ? 0.0f : rho2 * invb;
-        obm |= (uint32_t)o << u;
         seen |= o;
         pos = o ? 0 : pos + 1;
         B = fmaf(av[u], B, bv[u]);
