@@ -60,11 +60,12 @@ struct Layout {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Complex columns per X~^* W~ block: 32 (fewer re-reads of X~) when that still gives at
-// least 256 blocks, else 16.
+// Complex columns per X~^* W~ block: 32 (half the re-reads of X~, and fewer blocks than
+// compute units at 529 x 96 x 112, so that the G_X launches beside it find free ones)
+// unless that leaves fewer than 128 blocks, then 16.
 static int default_bcg(int n2, int nb, int r) {
   (void)r;
-  return (long)((n2 + 31) / 32) * nb >= 256 ? 32 : 16;
+  return (long)((n2 + 31) / 32) * nb >= 128 ? 32 : 16;
 }
 
 // Tunable execution shape of one context: the slice path (tctf::SlicePath, the fusion
