@@ -225,6 +225,7 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.r = p.r;
   q.nb = p.n3 / 2 + 1;
   q.spath = c->knobs.spath;
+  q.g_rows = q.spath == tctf::SPATH_COOP ? 1 : 0;   // the packed G's layout follows the slice path
   q.bcg = c->knobs.bcg;
   q.ycw = c->knobs.ycw;
   q.ny = (p.n2 + q.ycw - 1) / q.ycw;

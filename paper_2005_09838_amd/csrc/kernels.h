@@ -16,8 +16,11 @@ struct Plan {
   int mixed, force_eigen;
   hipStream_t stream;
 
-  float* gp;        // [n1][n3][n2] observed values (entry (i, j, k) at (i n3 + k) n2 + j, so the
-                    // tubes of one slice are read together); unobserved entries NaN-coded (run position)
+  float* gp;        // observed values, unobserved entries NaN-coded (run position); g_rows = 1:
+                    // [n1][n3][n2] (entry (i, j, k) at (i n3 + k) n2 + j: the cooperative slice
+                    // kernel reads 64 tubes per wave instruction), 0: [n1][n2][n3] (one thread
+                    // per tube or per row reads its own run of entries)
+  int g_rows;
   void* wt;         // W~ [n1][nb][n2] float2 (FP32) or packed bf16x2 (mixed)
   float2* zt;       // Z~ [n1][nb][n2]
   float2* xt;       // X~ [nb][r][n1]

@@ -253,7 +253,7 @@ __global__ void k_adj_tube_inv(const T* __restrict__ in, long ibs, long ips, lon
 __global__ void __launch_bounds__(256) k_adj_wstep(const double* __restrict__ wbar, const double* __restrict__ w,
                                                    const float* __restrict__ gp, double* __restrict__ zbar,
                                                    double* __restrict__ cbuf, int n1, int n2, int n3, double mu,
-                                                   double rho2, double* __restrict__ part) {
+                                                   double rho2, int g_rows, double* __restrict__ part) {
   __shared__ double red[16];
   const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double smu = 0.0, srho = 0.0;
@@ -261,7 +261,9 @@ __global__ void __launch_bounds__(256) k_adj_wstep(const double* __restrict__ wb
     const long i = row / n3, k = row % n3;
     const long base = i * n2 * n3 + k;   // element (i, j, k) at base + j n3
     auto deg = [&](int j) { return n2 == 1 ? 0.0 : ((j == 0 || j == n2 - 1) ? 1.0 : 2.0); };
-    auto unobs = [&](int j) { return is_unobserved(gp[(i * n3 + k) * n2 + j]); };   // packed G: [n1][n3][n2]
+    auto unobs = [&](int j) {   // packed G by rows or by tubes (Plan::g_rows)
+      return is_unobserved(gp[g_rows ? (i * n3 + k) * n2 + j : base + (long)j * n3]);
+    };
     double cprev = 0.0, dprev = 0.0;
     bool uprev = false;
     for (int j = 0; j < n2; ++j) {
@@ -442,7 +444,8 @@ void launch_adjoint_step(const Plan& p, const AdjWork& w, const AdjState& in, co
   tube_inv<float2>(p, out.wt, n2, (long)nb * n2, 1, w.w1s, (long)n2 * n3, n3, n1, n2, 1.0 / n3);
   // step 4: W-step adjoint -> z_bar, and the mu, rho2 adjoints
   const int wblk = (int)(((long)n1 * n3 + 255) / 256);
-  k_adj_wstep<<<wblk, 256, 0, p.stream>>>(w_bar, w.w1s, p.gp, w.zbar, w.cbuf, n1, n2, n3, p.mu, p.rho2, w.part);
+  k_adj_wstep<<<wblk, 256, 0, p.stream>>>(w_bar, w.w1s, p.gp, w.zbar, w.cbuf, n1, n2, n3, p.mu, p.rho2, p.g_rows,
+                                          w.part);
   k_adj_reduce2<<<1, 256, 0, p.stream>>>(w.part, wblk, theta, 0, 2);
   // step 3: Z~_bar = ifft(Z_bar) on the stored frequencies; X~+_bar += Z~_bar Y~+^*,
   // Y~+_bar += X~+^* Z~_bar

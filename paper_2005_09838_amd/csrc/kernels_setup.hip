@@ -10,17 +10,19 @@ size_t wt_elem_bytes(const Plan& p) { return p.mixed ? 4 : 8; }
 // be finite); unobserved ones become NaNs carrying their position in the run of
 // consecutive unobserved entries (section 3.3: the equality constraints of the W-step
 // are eliminated row by row, leaving one tridiagonal system per run).  The packed copy is
-// stored row by row, [n1][n3][n2]: the slice kernels read entry (i, j, k) for consecutive
-// tubes j at once.
+// stored row by row, [n1][n3][n2], for the cooperative slice kernel (a wavefront reads entry
+// (i, j, k) for 64 consecutive tubes j at once), else like G, [n1][n2][n3]: kernels with
+// one thread per tube or per row then read contiguous runs, and each wavefront keeps more
+// cache lines in flight.
 __global__ void k_pack_g(const float* __restrict__ g, const uint8_t* __restrict__ om,
-                         float* __restrict__ gp, int n1, int n2, int n3, int* flag) {
+                         float* __restrict__ gp, int n1, int n2, int n3, int rows, int* flag) {
   const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= (long)n1 * n3) return;
   const long i = row / n3, k = row % n3;
   int run_start = -1;          // index of the first unobserved entry of the current run
   bool seen_obs = false;
   for (int j = 0; j < n2; ++j) {
-    const long idx = (i * n2 + j) * n3 + k, out = (i * n3 + k) * n2 + j;
+    const long idx = (i * n2 + j) * n3 + k, out = rows ? (i * n3 + k) * n2 + j : idx;
     if (om[idx]) {
       const float v = g[idx];
       if (!isfinite(v)) atomicOr(flag, 1);
@@ -37,7 +39,8 @@ __global__ void k_pack_g(const float* __restrict__ g, const uint8_t* __restrict_
 
 void launch_pack_g(const Plan& p, const float* G, const uint8_t* omega) {
   const long rows = (long)p.n1 * p.n3;
-  k_pack_g<<<(unsigned)((rows + 255) / 256), 256, 0, p.stream>>>(G, omega, p.gp, p.n1, p.n2, p.n3, p.flag);
+  k_pack_g<<<(unsigned)((rows + 255) / 256), 256, 0, p.stream>>>(G, omega, p.gp, p.n1, p.n2, p.n3, p.g_rows,
+                                                                  p.flag);
 }
 
 // Reciprocal pivots of the W-step row systems (eq. (subquKKT)), in FP64 then rounded.

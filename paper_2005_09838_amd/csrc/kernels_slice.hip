@@ -122,12 +122,12 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
 #pragma unroll
       for (int q = 0; q < N; ++q) dst[q] = z[q];
     }
-    const float* g = gslice + j;   // entry q at g[q n2]
+    const float* g = gslice + (size_t)j * N;   // packed G by tubes on this path
     const int jw0 = (j - lane) >> 5;   // first flag word of this wave's tubes
     float facc = 0.0f;
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-      const float gv = g[(size_t)q * n2];
+      const float gv = g[q];
       const bool obs = !is_unobserved(gv);
       float wv, d;
       if (!thomas) {
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
     const uint32_t jb = 1u << (j & 31);
     if constexpr (MODE == SLICE_KKT) {
       // residuals of eq. (subquKKT): unobserved (W K_{mu rho2} - Z)_ij, observed W - G
-      const float* g = gslice + j;
+      const float* g = gslice + (size_t)j * N;
       float z[N];
       load_inverse_tube<N>(a.zt, i, j, a.nb, n2, z);
 #pragma unroll
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
           const double r = has_r ? (double)wrow[q + LD] : 0.0;
           fit = fmax(fit, fabs((1.0 + cj) * wq - a.rho2d * (l + r) - (double)z[q]));
         } else if (obs) {
-          ridge = fmax(ridge, fabs(wq - (double)g[(size_t)q * n2]));
+          ridge = fmax(ridge, fabs(wq - (double)g[q]));
         }
         sm = fmax(sm, fabs((double)z[q]));
       }
@@ -528,7 +528,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
   const bool act = j < n2;
   const bool thomas = MODE != SLICE_INIT && !a.w_from_g;
   float* row = zs + (size_t)(act ? j : 0) * LD;
-  const float* gtube = a.gp + i * n2 * N + (act ? j : 0);   // entry q at gtube[q n2]: a wave reads 64 tubes at once
+  const float* gtube = a.gp + i * n2 * N + (act ? j : 0);   // packed G by rows on this path: entry q at gtube[q n2]
 
   for (int e = tid; e < 4 * n2; e += nt) tab[e] = a.wtab[e];
   tube_twiddles<N>(twm, twn);

@@ -92,14 +92,13 @@ __global__ void __launch_bounds__(256) k_gen_wstep(const float* __restrict__ zsp
   const bool solve = mode != SLICE_INIT && !w_from_g;
   double fit = 0.0, ridge = 0.0, sm = 0.0;
   for (int k = threadIdx.x; k < n3; k += blockDim.x) {
-    const long base = i * n2 * n3 + k;   // entry (i, j, k) at base + j n3
-    const float* grow = gp + (i * n3 + k) * n2;   // packed G: entry (i, j, k) at grow[j]
+    const long base = i * n2 * n3 + k;   // entry (i, j, k) at base + j n3 (packed G too, on this path)
     auto deg = [&](int j) { return n2 == 1 ? 0.0f : ((j == 0 || j == n2 - 1) ? 1.0f : 2.0f); };
     if (solve) {
       float cp = 0.0f, dp = 0.0f;
       for (int j = 0; j < n2; ++j) {
         const long e = base + (long)j * n3;
-        const float g = grow[j];
+        const float g = gp[e];
         float c, d;
         if (!is_unobserved(g)) {
           c = 0.0f;
@@ -124,7 +123,7 @@ __global__ void __launch_bounds__(256) k_gen_wstep(const float* __restrict__ zsp
     } else {
       for (int j = 0; j < n2; ++j) {
         const long e = base + (long)j * n3;
-        const float g = grow[j];
+        const float g = gp[e];
         wsp[e] = is_unobserved(g) ? 0.0f : g;
       }
     }
@@ -132,12 +131,12 @@ __global__ void __launch_bounds__(256) k_gen_wstep(const float* __restrict__ zsp
     for (int j = 0; j < n2; ++j) {
       const long e = base + (long)j * n3;
       const float w = wsp[e], z = zsp[e];
-      const bool obs = !is_unobserved(grow[j]);
+      const bool obs = !is_unobserved(gp[e]);
       if (w_out) w_out[e] = w;
       if (mode == SLICE_KKT) {
         const double l = j > 0 ? (double)wsp[e - n3] : 0.0, r = j + 1 < n2 ? (double)wsp[e + n3] : 0.0;
         if (!obs && solve) fit = fmax(fit, fabs((1.0 + mu + rho2 * deg(j)) * w - rho2 * (l + r) - (double)z));
-        else if (obs) ridge = fmax(ridge, fabs((double)w - (double)grow[j]));
+        else if (obs) ridge = fmax(ridge, fabs((double)w - (double)gp[e]));
         sm = fmax(sm, fabs((double)z));
       } else {
         const double d = (double)z - (double)w;
