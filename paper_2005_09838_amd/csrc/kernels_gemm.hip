@@ -131,21 +131,150 @@ __global__ void __launch_bounds__(256) k_zgemm(const float2* __restrict__ xt, co
   }
 }
 
+// Mixed precision: the same product on the BF16 matrix cores (16 x 16 x 16 tiles, FP32
+// accumulation).  X~ and Y~ are rounded to BF16 and Z~ is stored as packed BF16 pairs, all
+// by stochastic rounding (bits from the element index and the iteration counter, a key per
+// array).  Z~ feeds only the W-step, a contraction, so its rounding is not amplified; A and
+// X~^* W~ stay FP32 / FP64, since the pseudo-inverses of the Grams multiply them.
+// Lane (m, q) supplies A[m][4 q + e] and B[4 q + e][m], e = 0..3, of each 16-deep K chunk:
+// in chunk c, K index 16 c + 4 q + e is (s, d) = (8 c + 2 q + e / 2, e % 2), so the lane's A
+// values are (re, im) of X~(row, s0) and X~(row, s0 + 1), s0 = 8 c + 2 q, and its B values
+// the signed parts of Y~(s0, j) and Y~(s0 + 1, j) (see Y' above).  Output tiles as k_zgemm's.
+typedef short v4s __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4f mfma16bf(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+#define ZKEY_X 0xdaa66d2bu   // rounding-bit keys of X~, Y~ and Z~ (W~ has its own)
+#define ZKEY_Y 0x3c6ef372u
+#define ZKEY_Z 0x78dde6e4u
+template <int RM>
+__global__ void __launch_bounds__(256) k_zgemm_bf(const float2* __restrict__ xt, const float2* __restrict__ yt,
+                                                  uint32_t* __restrict__ zt, int n1, int n2, int r, int nb,
+                                                  int npinv, PinvyArgs pa, const uint32_t* __restrict__ ctr) {
+  extern __shared__ __align__(16) unsigned char zsm[];
+  if ((int)blockIdx.x < npinv) {
+    pinvy_block(blockIdx.x, pa, zsm);
+    return;
+  }
+  uint32_t* ysh = (uint32_t*)zsm;   // [s][j] of the column chunk, packed BF16 pairs
+  const int bid = blockIdx.x - npinv, ntile = (n1 + ZG_ROWS - 1) / ZG_ROWS;
+  const int i0 = (bid % ntile) * ZG_ROWS, b = bid / ntile, tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
+  constexpr int KC = RM / 8;   // 16-deep K chunks over 2 RM
+  constexpr int YPER = RM * ZG_COLS / 256;
+  const uint32_t c0 = ctr[0] * 0x9e3779b9u;
+  const uint32_t kx = fmix32(c0 + ZKEY_X), ky = fmix32(c0 + ZKEY_Y), kz = fmix32(c0 + ZKEY_Z);
+  float2 yv[YPER];
+  auto load_y = [&](int j0) {
+    const int nc = min(ZG_COLS, n2 - j0);
+#pragma unroll
+    for (int u = 0; u < YPER; ++u) {
+      const int e = tid + 256 * u, s = e / ZG_COLS, jj = e % ZG_COLS;
+      yv[u] = ld_or(yt, ((size_t)b * r + s) * n2 + j0 + jj, s < r && jj < nc, make_float2(0.f, 0.f));
+    }
+  };
+  load_y(0);
+  // A operands: X~(row, s0), X~(row, s0 + 1) of each chunk, rounded
+  const int row = i0 + 16 * w + m;
+  v4s a[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    uint32_t h[2];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int s = 8 * c + 2 * q + d;
+      const size_t ix = ((size_t)b * r + min(s, r - 1)) * n1 + min(row, n1 - 1);
+      const float2 xv = xt[ix];   // clamped into range, loaded unconditionally
+      const float2 x = (s < r && row < n1) ? xv : make_float2(0.f, 0.f);
+      h[d] = pack_bf16x2_sr(x.x, x.y, fmix32((uint32_t)ix ^ kx));
+    }
+    a[c] = v4s{(short)(h[0] & 0xffffu), (short)(h[0] >> 16), (short)(h[1] & 0xffffu), (short)(h[1] >> 16)};
+  }
+  const bool pair2 = (n2 & 1) == 0;   // rows start 8-byte aligned
+  for (int j0 = 0; j0 < n2; j0 += ZG_COLS) {
+    const int nc = min(ZG_COLS, n2 - j0);
+    if (j0 > 0) {
+      __syncthreads();   // every wavefront is done with the previous chunk
+      load_y(j0);
+    }
+#pragma unroll
+    for (int u = 0; u < YPER; ++u) {
+      const int e = tid + 256 * u, s = e / ZG_COLS, jj = e % ZG_COLS;
+      ysh[e] = pack_bf16x2_sr(yv[u].x, yv[u].y, fmix32((uint32_t)(((size_t)b * r + s) * n2 + j0 + jj) ^ ky));
+    }
+    __syncthreads();
+    const int ntiles = (2 * nc + 15) / 16;
+    for (int nt0 = 0; nt0 < ntiles; nt0 += 4) {
+      v4f acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        const int s0 = 8 * c + 2 * q;   // rows past r are zero in the chunk
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jj = min(8 * nt0 + 2 * m + (u >> 1), ZG_COLS - 1);
+          const uint32_t y0 = ysh[s0 * ZG_COLS + jj], y1 = ysh[(s0 + 1) * ZG_COLS + jj];
+          v4s bv;
+          if (u & 1) {   // column 2 j + 1: (Yi, Yr, Yi', Yr')
+            bv = v4s{(short)(y0 >> 16), (short)(y0 & 0xffffu), (short)(y1 >> 16), (short)(y1 & 0xffffu)};
+          } else {       // column 2 j: (Yr, -Yi, Yr', -Yi')
+            bv = v4s{(short)(y0 & 0xffffu), (short)((y0 >> 16) ^ 0x8000u), (short)(y1 & 0xffffu),
+                     (short)((y1 >> 16) ^ 0x8000u)};
+          }
+          acc[u] = mfma16bf(a[c], bv, acc[u]);
+        }
+      }
+      const int jc = 8 * nt0 + 2 * m;   // first of this lane's two complex columns in the chunk
+      if (jc < nc) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = i0 + 16 * w + 4 * q + t;
+          if (i < n1) {
+            const size_t e = ((size_t)i * nb + b) * n2 + j0 + jc;
+            const uint32_t z0 = pack_bf16x2_sr(acc[0][t], acc[1][t], fmix32((uint32_t)e ^ kz));
+            if (jc + 1 < nc) {
+              const uint32_t z1 = pack_bf16x2_sr(acc[2][t], acc[3][t], fmix32((uint32_t)(e + 1) ^ kz));
+              if (pair2) {
+                *(uint2*)(zt + e) = make_uint2(z0, z1);
+              } else {
+                zt[e] = z0;
+                zt[e + 1] = z1;
+              }
+            } else {
+              zt[e] = z0;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 void zgemm_set_attr(int r) {
-  if (pinvy_lds_bytes(r) > 65536)
+  if (pinvy_lds_bytes(r) > 65536) {
     (void)hipFuncSetAttribute((const void*)k_zgemm<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)pinvy_lds_bytes(r));
+    (void)hipFuncSetAttribute((const void*)k_zgemm_bf<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)pinvy_lds_bytes(r));
+  }
 }
 
 void launch_zgemm(const Plan& p, int with_pinv) {
   const int npinv = with_pinv ? p.nb : 0;
   const int grid = npinv + (p.n1 + ZG_ROWS - 1) / ZG_ROWS * p.nb;
   const int rm = p.r <= 8 ? 8 : (p.r <= 16 ? 16 : 32);
-  size_t lds = (size_t)rm * ZG_COLS * sizeof(float2);
+  size_t lds = (size_t)rm * ZG_COLS * (p.mixed ? sizeof(uint32_t) : sizeof(float2));
   if (with_pinv && pinvy_lds_bytes(p.r) > lds) lds = pinvy_lds_bytes(p.r);
   const PinvyArgs pa = pinvy_args(p);
-#define TCTF_ZGEMM(RM) \
-  k_zgemm<RM><<<grid, 256, lds, p.stream>>>(p.xt, p.yt, p.zt, p.n1, p.n2, p.r, p.nb, npinv, pa)
+#define TCTF_ZGEMM(RM)                                                                                         \
+  do {                                                                                                         \
+    if (p.mixed)                                                                                               \
+      k_zgemm_bf<RM><<<grid, 256, lds, p.stream>>>(p.xt, p.yt, (uint32_t*)p.zt, p.n1, p.n2, p.r, p.nb, npinv, pa, \
+                                                   p.ctr);                                                     \
+    else                                                                                                       \
+      k_zgemm<RM><<<grid, 256, lds, p.stream>>>(p.xt, p.yt, (float2*)p.zt, p.n1, p.n2, p.r, p.nb, npinv, pa);  \
+  } while (0)
   if (p.r <= 8) TCTF_ZGEMM(8);
   else if (p.r <= 16) TCTF_ZGEMM(16);
   else TCTF_ZGEMM(32);
