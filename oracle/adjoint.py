@@ -19,7 +19,7 @@ used below follow from that definition:
 * A = Re idft3(A~) (eq. (barAAk)):
                       A~_bar = ifft(A_bar)  (= dft3(A_bar) / m3).
 
-The step sizes are the common constant eta of reading R3, and the Grams G_Y = Y~Y~^* and
+The step sizes of eq. (updataXYW1) are one common constant eta, and the Grams G_Y = Y~Y~^* and
 G_X = X~^* H_rho1 X~ are taken to have full rank (then their pseudo-inverses of Lemma
 SVPMPI are inverses, P = I, and the updates of eq. (updataXYW1) simplify to
 

@@ -101,6 +101,20 @@ def test_mixed_precision_reaches_the_fp32_error(name):
     assert np.array_equal(b["W"], b2["W"])
 
 
+@pytest.mark.parametrize("name", ["od529x96x112_r16", "od144x288x28_r8_p40"])
+def test_mixed_precision_first_iterations_near_the_oracle(name):
+    """Mixed precision (BF16 W~ and Z~, Z~ = X~Y~ on the BF16 matrix cores from stochastically
+    rounded factors) two iterations from the oracle's start: W and Z within 1e-2 (relative
+    Frobenius) of the FP64 oracle.  BF16 keeps 8 significant bits, so a wrong operand
+    layout, sign or rounding key in the BF16 tiles would be off by far more."""
+    w, d = make_workload(name)
+    g = gpu_run(d, w.r, 2, precision="mixed")
+    st, _ = oracle_run(d, w.r, 2)
+    ew, ez = rel(g["W"], st.w), rel(g["Z"], oracle.z_of(st))
+    print(f"{name} mixed, 2 it: W {ew:.2e} Z {ez:.2e}", flush=True)
+    assert ew < 1e-2 and ez < 1e-2
+
+
 def test_stage_profile_records_each_launch():
     """tctf_profile brackets exactly the launches of the chosen stages; results are unchanged."""
     d = make_inputs(40, 30, 12, 4, p=0.4, seed=8)
