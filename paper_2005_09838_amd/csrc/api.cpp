@@ -147,6 +147,7 @@ struct tctf_ctx {
   Layout lay;
   unsigned char* ws;
   int device;
+  int ncu;   // compute units of the device
   int64_t iters;
   bool term_valid;
   Knobs knobs;
@@ -225,6 +226,7 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.r = p.r;
   q.nb = p.n3 / 2 + 1;
   q.spath = c->knobs.spath;
+  q.ncu = c->ncu;
   q.g_rows = q.spath == tctf::SPATH_COOP ? 1 : 0;   // the packed G's layout follows the slice path
   q.bcg = c->knobs.bcg;
   q.ycw = c->knobs.ycw;
@@ -361,6 +363,8 @@ static tctf_status ctx_init(tctf_ctx* c, const tctf_params* prm, const float* G,
   c->knobs = knobs ? *knobs : default_knobs(*prm);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) return fail(TCTF_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  e = hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e != hipSuccess) return fail(TCTF_E_HIP, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
   fill_plan(c, (hipStream_t)hip_stream);
   const Plan& p = c->plan;
   tctf::slice_set_attr(p.n3, tctf::slice_launch_lds_bytes(p));
@@ -1135,9 +1139,12 @@ static tctf_status batch_graph(tctf_batch* b, int k) {
       for (size_t m = q; m < b->members.size() && s == TCTF_OK; m += nbr) {
         tctf_ctx* c = b->members[m];
         const hipStream_t user = c->plan.stream;
+        const int ncu = c->plan.ncu;
         c->plan.stream = b->streams[q];
+        c->plan.ncu = 0;   // members share the compute units: no launch reserves one for itself
         s = enqueue_iteration(c);
         c->plan.stream = user;
+        c->plan.ncu = ncu;
       }
     }
     if (e == hipSuccess) e = hipEventRecord(b->done_ev[q], b->streams[q]);

@@ -12,6 +12,7 @@ struct Plan {
   int bcg;                     // complex columns per X~^* W~ block (16 or 32)
   int ny, ycw;                 // column blocks of the Y-step per frequency, columns per block
   int spath;                   // slice path: SPATH_COOP, SPATH_THREAD or SPATH_SPLIT
+  int ncu;                     // compute units of the device
   double mu, rho1, rho2, eta;
   int mixed, force_eigen;
   hipStream_t stream;

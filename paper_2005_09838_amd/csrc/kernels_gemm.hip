@@ -644,10 +644,14 @@ __global__ void __launch_bounds__(256) k_gramx_inv(const cd* __restrict__ part, 
 
 int gramx_groups(int n1) { return (n1 + GXR - 1) / GXR; }
 
+// LDS the inversion launch asks for when the X~^* W~ product beside it leaves compute units
+// free: more than a compute unit (160 KB) holds next to one product block, so the inversions
+// run on the free units instead of sharing one with the product (FP64 arithmetic beside FP64
+// matrix-core work there ran 2.5 times slower)
+#define GXI_LDS_ALONE (150 * 1024)
 void gramx_set_attr(int r) {
-  if (pinvy_lds_bytes(r) > 65536)
-    (void)hipFuncSetAttribute((const void*)k_gramx_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)pinvy_lds_bytes(r));
+  (void)r;
+  (void)hipFuncSetAttribute((const void*)k_gramx_inv, hipFuncAttributeMaxDynamicSharedMemorySize, GXI_LDS_ALONE);
 }
 
 void launch_gramx(const Plan& p) {
@@ -665,7 +669,9 @@ void launch_gramx(const Plan& p) {
   if (p.r <= 8) k_gramx_part<8><<<grid, 256, 0, p.stream>>>(p.xt, p.n1, p.r, ngrp, p.gxpart);
   else if (p.r <= 16) k_gramx_part<16><<<grid, 256, 0, p.stream>>>(p.xt, p.n1, p.r, ngrp, p.gxpart);
   else k_gramx_part<32><<<grid, 256, 0, p.stream>>>(p.xt, p.n1, p.r, ngrp, p.gxpart);
-  k_gramx_inv<<<p.nb, 256, pinvy_lds_bytes(p.r), p.stream>>>(p.gxpart, ngrp, p.r, go);
+  size_t lds = pinvy_lds_bytes(p.r);
+  if ((long)((p.n2 + p.bcg - 1) / p.bcg) * p.nb < p.ncu && lds < GXI_LDS_ALONE) lds = GXI_LDS_ALONE;
+  k_gramx_inv<<<p.nb, 256, lds, p.stream>>>(p.gxpart, ngrp, p.r, go);
 }
 
 // ---------------------------------------------------------------- X~^* W~
