@@ -4,8 +4,9 @@
 A "step" is one full iteration of the method (X-step, Y-step, Z = X*Y, W-step and the
 tube transforms) over the synthetic 529 OD x 96 slot x 112 day traffic tensor (40 %
 sampled), with every input resident in device memory.  Both precisions are run: FP32, and
-mixed (W~ and Z~ stored in BF16, Z~ = X~ Y~ on the BF16 matrix cores, factors FP32, FP32
-accumulation; FP64 r x r Grams / pseudo-inverses / objective).  The equal-error protocol compares their completion error
+mixed (W~ stored in BF16; Z~ = X~Y~ and A = W~Y~^* on the BF16 matrix cores with the FP32
+factors split into two BF16 parts, FP32 accumulation; X~^* W~ in FP64; FP64 r x r Grams /
+pseudo-inverses / objective).  The equal-error protocol compares their completion error
 (RSE against the full synthetic tensor): FP32 after --rse-iters iterations sets RSE32, and
 the mixed run's first iteration with RSE <= RSE32 (1 + 5e-3) is reported (None if none).
 
@@ -65,7 +66,7 @@ def stage_bytes(stage, n1, n2, n3, r, mixed):
     fx, fy = 8 * nb * r * n1, 8 * nb * r * n2
     return {
         "slice": 4 * n1 * n2 * n3 + sw * nh,             # read G, write W~
-        "zgemm": fx + fy + sw * nh,                      # read X~, Y~, write Z~ (BF16 pairs when mixed)
+        "zgemm": fx + fy + 8 * nh,                       # read X~, Y~, write Z~
         "agemm": sw * nh + fy + fx + fx,                 # read W~, Y~, X~, write the X right-hand side
         "hsolve": 2 * fx,                                # read the right-hand side, write X~
         "bgemm": sw * nh + fx + fy,                      # read W~ and X~, write X~^* W~

@@ -54,17 +54,17 @@ typedef enum {
 typedef enum {
   TCTF_FP32 = 0,        /* FP32 storage and products; the reduction over n1 of X~^* W~
                            accumulates in FP64; r x r Grams, pseudo-inverses, objective FP64 */
-  TCTF_MIXED_BF16 = 1   /* W~ and Z~ stored in BF16 (half the bytes of their writes and
-                           reads), rounded stochastically with counter-based rounding bits
-                           keyed by the entry and the iteration (deterministic and resumable;
-                           unlike round-to-nearest its error does not repeat from one iteration
-                           to the next, so the iteration does not accumulate it); Z~ = X~ Y~
-                           runs on the BF16 matrix cores from stochastically rounded X~, Y~
-                           with FP32 accumulation (step 3 feeds only the W-step, which does
-                           not amplify rounding); A = W~ Y~^* takes the BF16 W~ and FP32 Y~
-                           and accumulates in FP32, X~^* W~ in FP64 (the pseudo-inverses of
-                           the Grams multiply both); factors, G and W stay FP32; r x r Grams,
-                           pseudo-inverses and objective FP64                                */
+  TCTF_MIXED_BF16 = 1   /* W~ stored in BF16 (half the bytes of its write and reads), rounded
+                           stochastically with counter-based rounding bits keyed by the entry
+                           and the iteration (deterministic and resumable; unlike
+                           round-to-nearest its error does not repeat from one iteration to
+                           the next, so the iteration does not accumulate it); the slice
+                           products Z~ = X~ Y~ and A = W~ Y~^* run on the BF16 matrix cores
+                           with FP32 accumulation, the BF16 W~ as it is and each FP32 factor
+                           split into two BF16 parts (hi + lo: three or two products, errors
+                           near 2^-17); X~^* W~ accumulates in FP64 (G_X^+ multiplies it);
+                           factors, G, Z~ and W stay FP32; r x r Grams, pseudo-inverses and
+                           objective FP64                                                    */
 } tctf_precision;
 
 typedef struct {

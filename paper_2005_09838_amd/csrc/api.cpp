@@ -240,7 +240,7 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.stream = stream;
   q.gp = (float*)(w + L.gp);
   q.wt = (void*)(w + L.wt);
-  q.zt = (void*)(w + L.zt);
+  q.zt = (float2*)(w + L.zt);
   q.xt = (float2*)(w + L.xt);
   q.yt = (float2*)(w + L.yt);
   q.rhs = (float2*)(w + L.rhs);

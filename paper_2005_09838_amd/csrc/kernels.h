@@ -23,7 +23,7 @@ struct Plan {
                     // per tube or per row reads its own run of entries)
   int g_rows;
   void* wt;         // W~ [n1][nb][n2] float2 (FP32) or packed bf16x2 (mixed)
-  void* zt;         // Z~ [n1][nb][n2] float2 (FP32) or packed bf16 pairs (mixed)
+  float2* zt;       // Z~ [n1][nb][n2]
   float2* xt;       // X~ [nb][r][n1]
   float2* yt;       // Y~ [nb][r][n2]
   float2* rhs;      // right-hand side of the H_rho1 solve [nb][r][n1]

@@ -132,10 +132,13 @@ __global__ void __launch_bounds__(256) k_zgemm(const float2* __restrict__ xt, co
 }
 
 // Mixed precision: the same product on the BF16 matrix cores (16 x 16 x 16 tiles, FP32
-// accumulation).  X~ and Y~ are rounded to BF16 and Z~ is stored as packed BF16 pairs, all
-// by stochastic rounding (bits from the element index and the iteration counter, a key per
-// array).  Z~ feeds only the W-step, a contraction, so its rounding is not amplified; A and
-// X~^* W~ stay FP32 / FP64, since the pseudo-inverses of the Grams multiply them.
+// accumulation).  Each FP32 factor value v is split into v_hi = bf16(v) and v_lo =
+// bf16(v - v_hi) (round to nearest), and Z' = X'_hi Y'_hi + X'_hi Y'_lo + X'_lo Y'_hi: three
+// BF16 products that keep about 16 bits of each operand, so Z~ carries errors near 2^-17
+// relative instead of BF16's 2^-9.  Z~ feeds the W-step directly: BF16-sized noise there,
+// new every iteration, made the iterate wander along the weakly determined directions of
+// the completion (the RSE drifting by a few percent over thousands of iterations), while the
+// split products leave it where the FP32 iteration goes.
 // Lane (m, q) supplies A[m][4 q + e] and B[4 q + e][m], e = 0..3, of each 16-deep K chunk:
 // in chunk c, K index 16 c + 4 q + e is (s, d) = (8 c + 2 q + e / 2, e % 2), so the lane's A
 // values are (re, im) of X~(row, s0) and X~(row, s0 + 1), s0 = 8 c + 2 q, and its B values
@@ -144,26 +147,26 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ v4f mfma16bf(v4s a, v4s b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
-#define ZKEY_X 0xdaa66d2bu   // rounding-bit keys of X~, Y~ and Z~ (W~ has its own)
-#define ZKEY_Y 0x3c6ef372u
-#define ZKEY_Z 0x78dde6e4u
+// (hi, lo) BF16 parts of x, as the low and high halves of one word
+__device__ __forceinline__ uint32_t bf16_split(float x) {
+  const uint16_t h = f32_to_bf16(x);
+  return (uint32_t)h | ((uint32_t)f32_to_bf16(x - bf16_to_f32(h)) << 16);
+}
 template <int RM>
 __global__ void __launch_bounds__(256) k_zgemm_bf(const float2* __restrict__ xt, const float2* __restrict__ yt,
-                                                  uint32_t* __restrict__ zt, int n1, int n2, int r, int nb,
-                                                  int npinv, PinvyArgs pa, const uint32_t* __restrict__ ctr) {
+                                                  float2* __restrict__ zt, int n1, int n2, int r, int nb,
+                                                  int npinv, PinvyArgs pa) {
   extern __shared__ __align__(16) unsigned char zsm[];
   if ((int)blockIdx.x < npinv) {
     pinvy_block(blockIdx.x, pa, zsm);
     return;
   }
-  uint32_t* ysh = (uint32_t*)zsm;   // [s][j] of the column chunk, packed BF16 pairs
+  uint2* ysh = (uint2*)zsm;   // [s][j] of the column chunk: (re, im) split words
   const int bid = blockIdx.x - npinv, ntile = (n1 + ZG_ROWS - 1) / ZG_ROWS;
   const int i0 = (bid % ntile) * ZG_ROWS, b = bid / ntile, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
   constexpr int KC = RM / 8;   // 16-deep K chunks over 2 RM
   constexpr int YPER = RM * ZG_COLS / 256;
-  const uint32_t c0 = ctr[0] * 0x9e3779b9u;
-  const uint32_t kx = fmix32(c0 + ZKEY_X), ky = fmix32(c0 + ZKEY_Y), kz = fmix32(c0 + ZKEY_Z);
   float2 yv[YPER];
   auto load_y = [&](int j0) {
     const int nc = min(ZG_COLS, n2 - j0);
@@ -174,23 +177,25 @@ __global__ void __launch_bounds__(256) k_zgemm_bf(const float2* __restrict__ xt,
     }
   };
   load_y(0);
-  // A operands: X~(row, s0), X~(row, s0 + 1) of each chunk, rounded
+  // A operands: X~(row, s0), X~(row, s0 + 1) of each chunk, split
   const int row = i0 + 16 * w + m;
-  v4s a[KC];
+  v4s ahi[KC], alo[KC];
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
-    uint32_t h[2];
+    uint32_t h[4];
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       const int s = 8 * c + 2 * q + d;
-      const size_t ix = ((size_t)b * r + min(s, r - 1)) * n1 + min(row, n1 - 1);
-      const float2 xv = xt[ix];   // clamped into range, loaded unconditionally
+      const float2 xv = xt[((size_t)b * r + min(s, r - 1)) * n1 + min(row, n1 - 1)];   // clamped, unconditional
       const float2 x = (s < r && row < n1) ? xv : make_float2(0.f, 0.f);
-      h[d] = pack_bf16x2_sr(x.x, x.y, fmix32((uint32_t)ix ^ kx));
+      h[2 * d] = bf16_split(x.x);
+      h[2 * d + 1] = bf16_split(x.y);
     }
-    a[c] = v4s{(short)(h[0] & 0xffffu), (short)(h[0] >> 16), (short)(h[1] & 0xffffu), (short)(h[1] >> 16)};
+    ahi[c] = v4s{(short)(h[0] & 0xffffu), (short)(h[1] & 0xffffu), (short)(h[2] & 0xffffu), (short)(h[3] & 0xffffu)};
+    alo[c] = v4s{(short)(h[0] >> 16), (short)(h[1] >> 16), (short)(h[2] >> 16), (short)(h[3] >> 16)};
   }
-  const bool pair2 = (n2 & 1) == 0;   // rows start 8-byte aligned
+  float* zf = (float*)zt;
+  const bool vec4 = (n2 & 1) == 0;   // rows start 16-byte aligned
   for (int j0 = 0; j0 < n2; j0 += ZG_COLS) {
     const int nc = min(ZG_COLS, n2 - j0);
     if (j0 > 0) {
@@ -198,10 +203,7 @@ __global__ void __launch_bounds__(256) k_zgemm_bf(const float2* __restrict__ xt,
       load_y(j0);
     }
 #pragma unroll
-    for (int u = 0; u < YPER; ++u) {
-      const int e = tid + 256 * u, s = e / ZG_COLS, jj = e % ZG_COLS;
-      ysh[e] = pack_bf16x2_sr(yv[u].x, yv[u].y, fmix32((uint32_t)(((size_t)b * r + s) * n2 + j0 + jj) ^ ky));
-    }
+    for (int u = 0; u < YPER; ++u) ysh[tid + 256 * u] = make_uint2(bf16_split(yv[u].x), bf16_split(yv[u].y));
     __syncthreads();
     const int ntiles = (2 * nc + 15) / 16;
     for (int nt0 = 0; nt0 < ntiles; nt0 += 4) {
@@ -214,35 +216,38 @@ __global__ void __launch_bounds__(256) k_zgemm_bf(const float2* __restrict__ xt,
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int jj = min(8 * nt0 + 2 * m + (u >> 1), ZG_COLS - 1);
-          const uint32_t y0 = ysh[s0 * ZG_COLS + jj], y1 = ysh[(s0 + 1) * ZG_COLS + jj];
-          v4s bv;
+          const uint2 y0 = ysh[s0 * ZG_COLS + jj], y1 = ysh[(s0 + 1) * ZG_COLS + jj];   // (re, im) split words
+          v4s bh, bl;
           if (u & 1) {   // column 2 j + 1: (Yi, Yr, Yi', Yr')
-            bv = v4s{(short)(y0 >> 16), (short)(y0 & 0xffffu), (short)(y1 >> 16), (short)(y1 & 0xffffu)};
+            bh = v4s{(short)(y0.y & 0xffffu), (short)(y0.x & 0xffffu), (short)(y1.y & 0xffffu), (short)(y1.x & 0xffffu)};
+            bl = v4s{(short)(y0.y >> 16), (short)(y0.x >> 16), (short)(y1.y >> 16), (short)(y1.x >> 16)};
           } else {       // column 2 j: (Yr, -Yi, Yr', -Yi')
-            bv = v4s{(short)(y0 & 0xffffu), (short)((y0 >> 16) ^ 0x8000u), (short)(y1 & 0xffffu),
-                     (short)((y1 >> 16) ^ 0x8000u)};
+            bh = v4s{(short)(y0.x & 0xffffu), (short)((y0.y & 0xffffu) ^ 0x8000u), (short)(y1.x & 0xffffu),
+                     (short)((y1.y & 0xffffu) ^ 0x8000u)};
+            bl = v4s{(short)(y0.x >> 16), (short)((y0.y >> 16) ^ 0x8000u), (short)(y1.x >> 16),
+                     (short)((y1.y >> 16) ^ 0x8000u)};
           }
-          acc[u] = mfma16bf(a[c], bv, acc[u]);
+          acc[u] = mfma16bf(alo[c], bh, acc[u]);
+          acc[u] = mfma16bf(ahi[c], bl, acc[u]);
+          acc[u] = mfma16bf(ahi[c], bh, acc[u]);
         }
       }
-      const int jc = 8 * nt0 + 2 * m;   // first of this lane's two complex columns in the chunk
-      if (jc < nc) {
+      const int col = 16 * nt0 + 4 * m;   // first of this lane's four floats in the chunk's 2 nc
+      if (col < 2 * nc) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int i = i0 + 16 * w + 4 * q + t;
           if (i < n1) {
-            const size_t e = ((size_t)i * nb + b) * n2 + j0 + jc;
-            const uint32_t z0 = pack_bf16x2_sr(acc[0][t], acc[1][t], fmix32((uint32_t)e ^ kz));
-            if (jc + 1 < nc) {
-              const uint32_t z1 = pack_bf16x2_sr(acc[2][t], acc[3][t], fmix32((uint32_t)(e + 1) ^ kz));
-              if (pair2) {
-                *(uint2*)(zt + e) = make_uint2(z0, z1);
+            float* dst = zf + (((size_t)i * nb + b) * n2 + j0) * 2 + col;
+            if (col + 4 <= 2 * nc) {
+              if (vec4) {
+                *(float4*)dst = make_float4(acc[0][t], acc[1][t], acc[2][t], acc[3][t]);
               } else {
-                zt[e] = z0;
-                zt[e + 1] = z1;
+                ((float2*)dst)[0] = make_float2(acc[0][t], acc[1][t]);
+                ((float2*)dst)[1] = make_float2(acc[2][t], acc[3][t]);
               }
             } else {
-              zt[e] = z0;
+              *(float2*)dst = make_float2(acc[0][t], acc[1][t]);
             }
           }
         }
@@ -264,16 +269,15 @@ void launch_zgemm(const Plan& p, int with_pinv) {
   const int npinv = with_pinv ? p.nb : 0;
   const int grid = npinv + (p.n1 + ZG_ROWS - 1) / ZG_ROWS * p.nb;
   const int rm = p.r <= 8 ? 8 : (p.r <= 16 ? 16 : 32);
-  size_t lds = (size_t)rm * ZG_COLS * (p.mixed ? sizeof(uint32_t) : sizeof(float2));
+  size_t lds = (size_t)rm * ZG_COLS * sizeof(float2);
   if (with_pinv && pinvy_lds_bytes(p.r) > lds) lds = pinvy_lds_bytes(p.r);
   const PinvyArgs pa = pinvy_args(p);
 #define TCTF_ZGEMM(RM)                                                                                         \
   do {                                                                                                         \
     if (p.mixed)                                                                                               \
-      k_zgemm_bf<RM><<<grid, 256, lds, p.stream>>>(p.xt, p.yt, (uint32_t*)p.zt, p.n1, p.n2, p.r, p.nb, npinv, pa, \
-                                                   p.ctr);                                                     \
+      k_zgemm_bf<RM><<<grid, 256, lds, p.stream>>>(p.xt, p.yt, p.zt, p.n1, p.n2, p.r, p.nb, npinv, pa);        \
     else                                                                                                       \
-      k_zgemm<RM><<<grid, 256, lds, p.stream>>>(p.xt, p.yt, (float2*)p.zt, p.n1, p.n2, p.r, p.nb, npinv, pa);  \
+      k_zgemm<RM><<<grid, 256, lds, p.stream>>>(p.xt, p.yt, p.zt, p.n1, p.n2, p.r, p.nb, npinv, pa);           \
   } while (0)
   if (p.r <= 8) TCTF_ZGEMM(8);
   else if (p.r <= 16) TCTF_ZGEMM(16);
@@ -300,7 +304,7 @@ __global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __r
                                                const cd* __restrict__ qy, const int* __restrict__ qy_zero,
                                                float2* __restrict__ rhs, int n1, int n2, int r, int nb,
                                                double eta, double rho1, int raw_a, uint32_t* ctr) {
-  __shared__ __align__(16) float2 ysh[RM * AG_COLS];   // [s][j] of the column chunk
+  __shared__ __align__(16) float2 ysh[RM * AG_COLS];   // [s][j] of the column chunk (MIXED: split words)
   __shared__ __align__(16) float2 ash[AG_ROWS * RM];   // A rows, then the results
   __shared__ __align__(16) cd gs[RM * RM];             // G_Y^+
   const int i0 = blockIdx.x * AG_ROWS, b = blockIdx.y, tid = threadIdx.x;
@@ -343,35 +347,54 @@ __global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __r
 #pragma unroll
     for (int u = 0; u < YPER; ++u) {
       const int e = tid + 256 * u, s = e / AG_COLS, jj = e % AG_COLS;
-      ysh[e] = (s < r && jj < nc) ? yv[u] : make_float2(0.f, 0.f);
+      const float2 y = (s < r && jj < nc) ? yv[u] : make_float2(0.f, 0.f);
+      if constexpr (MIXED) ((uint2*)ysh)[e] = make_uint2(bf16_split(y.x), bf16_split(y.y));
+      else ysh[e] = y;
     }
     __syncthreads();
 #pragma unroll
     for (int g = 0; g < AG_COLS / 8; ++g) {
       if (g < ngroups) {
         const int valid = row < n1 ? min(2, nc - (8 * g + 2 * q)) : 0;
-        float2 a0, a1;
         if constexpr (MIXED) {
-          a0 = unpack_bf16x2(lo[g]);
-          a1 = unpack_bf16x2(hi[g]);
-        } else {
-          a0 = lo[g];
-          a1 = hi[g];
-        }
-        const float2 z = make_float2(0.f, 0.f);
-        const float4 wa = make_float4(valid > 0 ? a0.x : z.x, valid > 0 ? a0.y : z.y, valid > 1 ? a1.x : z.x,
-                                      valid > 1 ? a1.y : z.y);
+          // BF16 matrix cores: this lane's four K values are the two packed W~ words as they
+          // are (exact), Y~ enters split into its hi and lo BF16 parts (two products)
+          const uint32_t w0 = valid > 0 ? lo[g] : 0u, w1 = valid > 1 ? hi[g] : 0u;
+          const v4s av = v4s{(short)(w0 & 0xffffu), (short)(w0 >> 16), (short)(w1 & 0xffffu), (short)(w1 >> 16)};
 #pragma unroll
-        for (int u = 0; u < NNT; ++u) {
-          const int s = min((16 * u + m) >> 1, r - 1);   // columns past 2r are dropped below
-          const float4 y2 = *(const float4*)&ysh[s * AG_COLS + 8 * g + 2 * q];   // Y~(s, j), Y~(s, j + 1)
-          // e = 0: (Yr, Yi, Yr', Yi');  e = 1: (-Yi, Yr, -Yi', Yr')
-          const float b0 = eodd ? -y2.y : y2.x, b1 = eodd ? y2.x : y2.y;
-          const float b2 = eodd ? -y2.w : y2.z, b3 = eodd ? y2.z : y2.w;
-          acc[u] = mfma4(wa.x, b0, acc[u]);
-          acc[u] = mfma4(wa.y, b1, acc[u]);
-          acc[u] = mfma4(wa.z, b2, acc[u]);
-          acc[u] = mfma4(wa.w, b3, acc[u]);
+          for (int u = 0; u < NNT; ++u) {
+            const int s = min((16 * u + m) >> 1, r - 1);   // columns past 2r are dropped below
+            const uint4 y2 = *(const uint4*)&((const uint2*)ysh)[s * AG_COLS + 8 * g + 2 * q];   // split (re, im) of Y~(s, j), Y~(s, j + 1)
+            // e = 0: (Yr, Yi, Yr', Yi');  e = 1: (-Yi, Yr, -Yi', Yr'), per part
+            v4s bh, bl;
+            if (eodd) {
+              bh = v4s{(short)((y2.y & 0xffffu) ^ 0x8000u), (short)(y2.x & 0xffffu), (short)((y2.w & 0xffffu) ^ 0x8000u),
+                       (short)(y2.z & 0xffffu)};
+              bl = v4s{(short)((y2.y >> 16) ^ 0x8000u), (short)(y2.x >> 16), (short)((y2.w >> 16) ^ 0x8000u),
+                       (short)(y2.z >> 16)};
+            } else {
+              bh = v4s{(short)(y2.x & 0xffffu), (short)(y2.y & 0xffffu), (short)(y2.z & 0xffffu), (short)(y2.w & 0xffffu)};
+              bl = v4s{(short)(y2.x >> 16), (short)(y2.y >> 16), (short)(y2.z >> 16), (short)(y2.w >> 16)};
+            }
+            acc[u] = mfma16bf(av, bl, acc[u]);
+            acc[u] = mfma16bf(av, bh, acc[u]);
+          }
+        } else {
+          const float2 a0 = lo[g], a1 = hi[g], z = make_float2(0.f, 0.f);
+          const float4 wa = make_float4(valid > 0 ? a0.x : z.x, valid > 0 ? a0.y : z.y, valid > 1 ? a1.x : z.x,
+                                        valid > 1 ? a1.y : z.y);
+#pragma unroll
+          for (int u = 0; u < NNT; ++u) {
+            const int s = min((16 * u + m) >> 1, r - 1);   // columns past 2r are dropped below
+            const float4 y2 = *(const float4*)&ysh[s * AG_COLS + 8 * g + 2 * q];   // Y~(s, j), Y~(s, j + 1)
+            // e = 0: (Yr, Yi, Yr', Yi');  e = 1: (-Yi, Yr, -Yi', Yr')
+            const float b0 = eodd ? -y2.y : y2.x, b1 = eodd ? y2.x : y2.y;
+            const float b2 = eodd ? -y2.w : y2.z, b3 = eodd ? y2.z : y2.w;
+            acc[u] = mfma4(wa.x, b0, acc[u]);
+            acc[u] = mfma4(wa.y, b1, acc[u]);
+            acc[u] = mfma4(wa.z, b2, acc[u]);
+            acc[u] = mfma4(wa.w, b3, acc[u]);
+          }
         }
       }
     }

@@ -31,7 +31,7 @@ namespace tctf {
 #define SLICE_THREADS 256
 
 struct SliceArgs {
-  const void* zt;        // Z~: float2, or packed BF16 pairs when mixed
+  const float2* zt;
   const float* gp;
   const float* wtab;
   void* wt;
@@ -48,35 +48,17 @@ struct SliceArgs {
   PinvyArgs pa;
 };
 
-// Address of element e of Z~ in its storage (float2, or packed BF16 pairs when mixed).
-__device__ __forceinline__ const void* zsrc(const SliceArgs& a, size_t e) {
-  return a.mixed ? (const void*)((const uint32_t*)a.zt + e) : (const void*)((const float2*)a.zt + e);
-}
-
 template <int N>
-__device__ __forceinline__ void load_inverse_tube(const void* __restrict__ zt, int zb, size_t i, int j, int nb, int n2,
+__device__ __forceinline__ void load_inverse_tube(const float2* __restrict__ zt, size_t i, int j, int nb, int n2,
                                                   float (&z)[N]) {
   constexpr int NB = N / 2 + 1;
   float re[NB], im[NB];
-  if (zb) {   // packed BF16 pairs
-    const uint32_t* src = (const uint32_t*)zt + i * nb * n2 + j;
-    uint32_t raw[NB];
+  const float2* src = zt + i * nb * n2 + j;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) raw[b] = src[(size_t)b * n2];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const float2 v = unpack_bf16x2(raw[b]);
-      re[b] = v.x;
-      im[b] = v.y;
-    }
-  } else {
-    const float2* src = (const float2*)zt + i * nb * n2 + j;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const float2 v = src[(size_t)b * n2];
-      re[b] = v.x;
-      im[b] = v.y;
-    }
+  for (int b = 0; b < NB; ++b) {
+    const float2 v = src[(size_t)b * n2];
+    re[b] = v.x;
+    im[b] = v.y;
   }
   tube_inv<N>(re, im, z);
 }
@@ -124,12 +106,12 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
     float z[N];
     if (need_z) {
       if constexpr (LDSFFT) {
-        tube_inv_lds<N>(zsrc(a, i * a.nb * n2 + j), a.mixed, n2, row, twm, twn);
+        tube_inv_lds<N>(a.zt + i * a.nb * n2 + j, n2, row, twm, twn);
         constexpr float inv_m = 1.0f / M;
 #pragma unroll
         for (int q = 0; q < N; ++q) z[q] = row[TubeLds<N>::xpos(q)] * inv_m;
       } else {
-        load_inverse_tube<N>(a.zt, a.mixed, i, j, a.nb, n2, z);
+        load_inverse_tube<N>(a.zt, i, j, a.nb, n2, z);
       }
     } else {
 #pragma unroll
@@ -242,7 +224,7 @@ __global__ void __launch_bounds__(SLICE_THREADS) k_slice(SliceArgs a) {
       // residuals of eq. (subquKKT): unobserved (W K_{mu rho2} - Z)_ij, observed W - G
       const float* g = gslice + (size_t)j * N;
       float z[N];
-      load_inverse_tube<N>(a.zt, a.mixed, i, j, a.nb, n2, z);
+      load_inverse_tube<N>(a.zt, i, j, a.nb, n2, z);
 #pragma unroll
       for (int q = 0; q < N; ++q) {
         const bool obs = obits[q * nwr + jw] & jb;
@@ -555,7 +537,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
   // ---- 1. inverse transform of Z~(i, j, :) (natural order in the row)
   const bool need_z = !(MODE == SLICE_RESULT && a.w_from_g && a.z_out == nullptr);
   if (need_z) {
-    if (act) tube_inv_pre<N>(zsrc(a, i * a.nb * n2 + j), a.mixed, n2, row, twn, t, T);
+    if (act) tube_inv_pre<N>(a.zt + i * a.nb * n2 + j, n2, row, twn, t, T);
     __syncthreads();
     if (act) fft4_step_a<M1, M2, -1>(row, twm, t, T);
     __syncthreads();
@@ -645,7 +627,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
     if constexpr (MODE == SLICE_KKT) {
       if (t == 0) {
         float z[N];
-        load_inverse_tube<N>(a.zt, a.mixed, i, j, a.nb, n2, z);
+        load_inverse_tube<N>(a.zt, i, j, a.nb, n2, z);
 #pragma unroll
         for (int q = 0; q < N; ++q) {
           const bool obs = obits[q * nwr + jw] & jb;

@@ -22,21 +22,19 @@ __global__ void k_gen_twiddles(double2* __restrict__ twg, int n3) {
   twg[m] = make_double2(c, s);
 }
 
-// One thread per (tube (i, j), k).  z_out (optional): a copy of Z for the caller.  zb: Z~
-// stored as packed BF16 pairs (mixed precision) instead of float2.
-__global__ void __launch_bounds__(256) k_gen_inv(const void* __restrict__ zt, int zb, const double2* __restrict__ twg,
+// One thread per (tube (i, j), k).  z_out (optional): a copy of Z for the caller.
+__global__ void __launch_bounds__(256) k_gen_inv(const float2* __restrict__ zt, const double2* __restrict__ twg,
                                                  float* __restrict__ zsp, float* __restrict__ z_out, int n1, int n2,
                                                  int n3, int nb) {
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (long)n1 * n2 * n3) return;
   const int k = (int)(g % n3);
   const long t = g / n3, i = t / n2, j = t % n2;
-  const long e0 = i * nb * n2 + j;
+  const float2* src = zt + i * nb * n2 + j;
   double acc = 0.0;
   int m = 0;   // (b k) mod n3
   for (int b = 0; b < nb; ++b) {
-    const long e = e0 + (long)b * n2;
-    const float2 v = zb ? unpack_bf16x2(((const uint32_t*)zt)[e]) : ((const float2*)zt)[e];
+    const float2 v = src[(long)b * n2];
     const double2 w = twg[m];
     acc += bin_weight(b, n3) * ((double)v.x * w.x + (double)v.y * w.y);   // Re(e^{-i th} v)
     m += k;
@@ -180,8 +178,7 @@ void launch_slice_generic(const Plan& p, int mode, float* w_out, float* z_out, i
   const long n = (long)p.n1 * p.n2 * p.n3;
   const bool need_z = !(mode == SLICE_RESULT && w_from_g && z_out == nullptr);
   if (need_z)
-    k_gen_inv<<<(unsigned)((n + 255) / 256), 256, 0, p.stream>>>(p.zt, p.mixed, p.twg, p.zsp, z_out, p.n1, p.n2,
-                                                                 p.n3, p.nb);
+    k_gen_inv<<<(unsigned)((n + 255) / 256), 256, 0, p.stream>>>(p.zt, p.twg, p.zsp, z_out, p.n1, p.n2, p.n3, p.nb);
   else
     launch_zero(p, p.zsp, (size_t)n * 4);
   const int threads = p.n3 >= 256 ? 256 : ((p.n3 + 63) / 64) * 64;

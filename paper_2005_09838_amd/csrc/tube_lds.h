@@ -85,30 +85,16 @@ __device__ __forceinline__ void fft4_lds(float* row, const float2* __restrict__ 
 //   E[b] = (X[b] + conj X[M-b]) / 2,  O[b] = (X[b] - conj X[M-b]) exp(-2 pi i b / N) / 2,
 //   C[b] = E[b] + i O[b],  C[M-b] = conj E[b] + i conj O[b],  c = inverse DFT_M(C).
 template <int N>
-__device__ __forceinline__ void tube_inv_lds(const void* __restrict__ srcv, int zb, size_t stride, float* row,
+__device__ __forceinline__ void tube_inv_lds(const float2* __restrict__ src, size_t stride, float* row,
                                              const float2* __restrict__ twm, const float2* __restrict__ twn) {
   using T = TubeLds<N>;
   constexpr int M = T::M;
   float xr[M + 1], xi[M + 1];
-  if (zb) {   // packed BF16 pairs
-    const uint32_t* src = (const uint32_t*)srcv;
-    uint32_t raw[M + 1];
 #pragma unroll
-    for (int b = 0; b <= M; ++b) raw[b] = src[(size_t)b * stride];
-#pragma unroll
-    for (int b = 0; b <= M; ++b) {
-      const float2 v = unpack_bf16x2(raw[b]);
-      xr[b] = v.x;
-      xi[b] = (b == 0 || b == M) ? 0.0f : v.y;
-    }
-  } else {
-    const float2* src = (const float2*)srcv;
-#pragma unroll
-    for (int b = 0; b <= M; ++b) {
-      const float2 v = src[(size_t)b * stride];
-      xr[b] = v.x;
-      xi[b] = (b == 0 || b == M) ? 0.0f : v.y;
-    }
+  for (int b = 0; b <= M; ++b) {
+    const float2 v = src[(size_t)b * stride];
+    xr[b] = v.x;
+    xi[b] = (b == 0 || b == M) ? 0.0f : v.y;
   }
 #pragma unroll
   for (int b = 0; b <= M / 2; ++b) {
@@ -209,38 +195,18 @@ __device__ __forceinline__ void fft4_step_c(float* row, int t, int T) {
 // pre-step of the inverse for the pairs b = t, t + T, ... <= M/2 (see tube_inv_lds); the
 // bins of four pairs are loaded (from clamped addresses, unconditionally) before any of them
 // is used, so a thread waits for one load latency per four pairs rather than per pair
-// (zb: the bins are packed BF16 pairs instead of float2; the storage branch sits outside
-// each batch of loads)
 template <int N>
-__device__ __forceinline__ void tube_inv_pre(const void* __restrict__ srcv, int zb, size_t stride, float* row,
+__device__ __forceinline__ void tube_inv_pre(const float2* __restrict__ src, size_t stride, float* row,
                                              const float2* __restrict__ twn, int t, int T) {
   constexpr int M = N / 2, B = 8;
   for (int b0 = t; b0 <= M / 2; b0 += B * T) {
     float2 xbv[B], xmv[B];
-    if (zb) {
-      const uint32_t* src = (const uint32_t*)srcv;
-      uint32_t rb[B], rm[B];
 #pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const int b = b0 + u * T;
-        const bool ok = b <= M / 2;
-        rb[u] = src[(size_t)(ok ? b : 0) * stride];
-        rm[u] = src[(size_t)(ok ? M - b : 0) * stride];
-      }
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        xbv[u] = unpack_bf16x2(rb[u]);
-        xmv[u] = unpack_bf16x2(rm[u]);
-      }
-    } else {
-      const float2* src = (const float2*)srcv;
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const int b = b0 + u * T;
-        const bool ok = b <= M / 2;
-        xbv[u] = src[(size_t)(ok ? b : 0) * stride];
-        xmv[u] = src[(size_t)(ok ? M - b : 0) * stride];
-      }
+    for (int u = 0; u < B; ++u) {
+      const int b = b0 + u * T;
+      const bool ok = b <= M / 2;
+      xbv[u] = src[(size_t)(ok ? b : 0) * stride];
+      xmv[u] = src[(size_t)(ok ? M - b : 0) * stride];
     }
 #pragma unroll
     for (int u = 0; u < B; ++u) {
