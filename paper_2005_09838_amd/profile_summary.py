@@ -183,7 +183,7 @@ def write_all_traffic(a) -> None:
         f.write("\n".join(lines) + "\n")
 
 
-MFMA_PEAK_TFLOPS = {"F32": 157.3, "F64": 78.6}
+MFMA_PEAK_TFLOPS = {"F32": 157.3, "F64": 78.6, "BF16": 2500.0}
 SIMDS = 1024          # 256 compute units x 4 SIMDs
 CLOCK_HZ = 2.4e9      # peak engine clock
 
@@ -191,30 +191,34 @@ CLOCK_HZ = 2.4e9      # peak engine clock
 def write_mfma(a) -> None:
     f32 = counter_means(a.counters, "SQ_INSTS_VALU_MFMA_MOPS_F32")
     f64 = counter_means(a.counters, "SQ_INSTS_VALU_MFMA_MOPS_F64")
+    bf16 = counter_means(a.counters, "SQ_INSTS_VALU_MFMA_MOPS_BF16")
     busy = counter_means(a.counters, "SQ_VALU_MFMA_BUSY_CYCLES")
     dur_ns = {r["Name"]: float(r["AverageNs"]) for r in kernel_stats(a.stats)}
     lines = [a.title, f"source_sha256: {source_digest()}", "",
-             f"{'kernel':40s} {'disp':>5s} {'GFLOP_f32':>9s} {'GFLOP_f64':>9s} {'mean_us':>8s} "
+             f"{'kernel':40s} {'disp':>5s} {'GFLOP_f32':>9s} {'GFLOP_f64':>9s} {'GFLOP_bf16':>10s} {'mean_us':>8s} "
              f"{'TFLOP/s':>8s} {'of_peak':>8s} {'busy%':>6s}"]
     rows = []
-    for k in f32:
-        fl32 = f32[k][0] * 512 / 1e9
-        fl64 = f64.get(k, (0.0, 0))[0] * 512 / 1e9
-        if fl32 + fl64 == 0.0 or k not in dur_ns:
+    for k in set(f32) | set(f64) | set(bf16):
+        fl = {t: c.get(k, (0.0, 0))[0] * 512 / 1e9 for t, c in (("F32", f32), ("F64", f64), ("BF16", bf16))}
+        tot = sum(fl.values())
+        if tot == 0.0 or k not in dur_ns:
             continue
         ns = dur_ns[k]
-        rate = (fl32 + fl64) / ns   # GFLOP per ns = 1e18 FLOP/s; in TFLOP/s below
-        rate_tf = rate * 1e6
-        peak = (fl32 * MFMA_PEAK_TFLOPS["F32"] + fl64 * MFMA_PEAK_TFLOPS["F64"]) / (fl32 + fl64)
+        rate_tf = tot / ns * 1e6   # GFLOP per ns = 1e6 TFLOP/s
+        # the time the flops would take at each type's dense peak, summed, against the duration
+        peak_us = sum(fl[t] * 1e9 / (MFMA_PEAK_TFLOPS[t] * 1e12) for t in fl) * 1e6
+        frac = peak_us / (ns / 1e3)
         util = 100.0 * busy.get(k, (0.0, 0))[0] / (ns * 1e-9 * CLOCK_HZ * SIMDS)
-        rows.append((fl32 + fl64, f"{_short(k)[:40]:40s} {f32[k][1]:5d} {fl32:9.4f} {fl64:9.4f} {ns / 1e3:8.2f} "
-                                  f"{rate_tf:8.2f} {rate_tf / peak:8.4f} {util:6.2f}"))
+        disp = max(c.get(k, (0.0, 0))[1] for c in (f32, f64, bf16))
+        rows.append((tot, f"{_short(k)[:40]:40s} {disp:5d} {fl['F32']:9.4f} {fl['F64']:9.4f} {fl['BF16']:10.4f} "
+                          f"{ns / 1e3:8.2f} {rate_tf:8.2f} {frac:8.4f} {util:6.2f}"))
     rows.sort(reverse=True)
     lines += [r[1] for r in rows]
     lines += ["",
               "GFLOP: SQ_INSTS_VALU_MFMA_MOPS_* x 512 per dispatch (counter run); mean_us: the kernel's",
-              "mean duration in the kernel-trace run; of_peak: against dense MFMA FP32 157.3 TFLOP/s,",
-              "FP64 78.6 TFLOP/s; busy%: SQ_VALU_MFMA_BUSY_CYCLES over mean duration x 2.4 GHz x 1024 SIMDs",
+              "mean duration in the kernel-trace run; of_peak: the time the flops take at the dense MFMA",
+              "peaks (FP32 157.3, FP64 78.6, BF16 2500 TFLOP/s) over that duration; busy%:",
+              "SQ_VALU_MFMA_BUSY_CYCLES over mean duration x 2.4 GHz x 1024 SIMDs",
               "(GRBM_GUI_ACTIVE of a counter-run dispatch includes the profiler's serialisation, so it",
               "is not used as the denominator)",
               "commands:"] + [f"  {c}" for c in a.command]

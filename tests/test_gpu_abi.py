@@ -115,6 +115,29 @@ def test_mixed_precision_first_iterations_near_the_oracle(name):
     assert ew < 1e-2 and ez < 1e-2
 
 
+def test_mixed_precision_stays_near_fp32_over_long_runs():
+    """Mixed precision over 4000 iterations at 529 x 96 x 112: BF16 rounding noise that is new
+    every iteration must not walk the iterate along the completion's weakly determined
+    directions (BF16-rounded Z~ did, by a few percent of RSE).  Every 400 iterations the RSE
+    is within the relative gap 5e-3 of the FP32 run's."""
+    from paper_2005_09838_amd import Completion
+    w, d = make_workload("od529x96x112_r16")
+    mk = lambda prec: Completion(to_dev(d["G"]), to_dev(d["omega"]), w.r, X0=to_dev(d["X0"]), Y0=to_dev(d["Y0"]),
+                                 precision=prec)
+    a, b = mk("fp32"), mk("mixed")
+    gaps = []
+    for _ in range(10):
+        a.step(400)
+        b.step(400)
+        ra = oracle.rse(a.result()["W"].cpu().numpy(), d["M"])
+        rb = oracle.rse(b.result()["W"].cpu().numpy(), d["M"])
+        gaps.append(rb / ra - 1.0)
+    print("mixed - fp32 RSE gaps every 400 it:", " ".join(f"{g:+.1e}" for g in gaps), flush=True)
+    assert max(abs(g) for g in gaps) <= 5e-3
+    a.close()
+    b.close()
+
+
 def test_stage_profile_records_each_launch():
     """tctf_profile brackets exactly the launches of the chosen stages; results are unchanged."""
     d = make_inputs(40, 30, 12, 4, p=0.4, seed=8)
