@@ -484,7 +484,9 @@ __device__ __forceinline__ void wstep_segmented(float* zs, int LD, const float* 
 
 // ---------------------------------------------------------------- cooperative slice kernel
 // The same three steps with T threads per tube (thread (t, j) = t * n2p + j, n2p = n2
-// rounded up to 64 so that every wave holds 64 consecutive tubes of one t).  The tube
+// rounded up to 64 so that every wavefront holds 64 consecutive tubes of one t; rounding to
+// 32 instead, which leaves no lane idle at n2 = 96, ran 2 % slower: the W-step then takes
+// five passes over the block instead of four).  The tube
 // transforms run through the tube's LDS row stage by stage.  T = M1 / 2 where that still
 // gives each thread at most two groups of every stage (else T = M1): the smaller blocks and
 // W-step segments of at most COOP_WS_L entries keep the registers low enough for three row
@@ -553,7 +555,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
   {
     constexpr float inv_m = 1.0f / M;
     constexpr int B = 7;   // G entries loaded ahead of their use: one load latency per seven
-    const int jw0 = (j - lane) >> 5;
     float facc = 0.0f;
     for (int q0 = t; q0 < N; q0 += B * T) {
       float gb[B];
@@ -581,8 +582,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7))) 
           row[q] = wv;
           if (a.z_out) a.z_out[(i * n2 + j) * N + q] = zq;
         }
+        // each half wavefront: the 32 tubes of flag word j / 32
         const uint64_t bal = __ballot(obs);
-        if (lane < 2 && jw0 + lane < nwr) obits[q * nwr + jw0 + lane] = (uint32_t)(bal >> (32 * lane));
+        if ((lane & 31) == 0 && act) obits[q * nwr + (j >> 5)] = (uint32_t)(bal >> lane);
       }
     }
     fit += (double)facc;
