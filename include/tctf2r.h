@@ -95,6 +95,12 @@ typedef struct {
                            of the shape reuse it); the workspace is sized for every shape.
                            Shapes change summation orders only.  0 (default): fixed rules.
                            tctf_complete_noalloc ignores it                                  */
+  int32_t xsolve;       /* X-update, first line of eq. (updataXYW1).  0 (default): where
+                           r <= 16 and H_rho1^{-1}'s entries c lambda^|i-j| fall below
+                           2^-40 c within 12 rows (rho1 <= 0.15), the A = W~Y~^* launch
+                           applies H_rho1^{-1} itself as that short stencil (with the mirror
+                           terms of the two end rows); otherwise, and with 1, a separate
+                           tridiagonal solve follows it.  The two agree to FP32 rounding   */
 } tctf_params;
 /* Sizes: n1 <= 8192, n2 <= 1024, n3 <= 8192.  For n3 in 1..16, 20, 24, 28, 32, 40, 48, 56,
  * 64, 84, 96, 112, 128 (the lengths the tube transform is generated for) with one slice
@@ -189,8 +195,9 @@ tctf_status tctf_rank_vector(tctf_ctx* c, int32_t* ranks);
 
 /* The execution shape in use: out[0] = slice path (1 fused, several threads per tube;
  * 2 fused, one thread per tube; 3 three launches), out[1] = columns per X~^* W~ block,
- * out[2] = columns per Y-step block, out[3] = 1 if it came from the process's tuning cache. */
-tctf_status tctf_tuning(tctf_ctx* c, int32_t out[4]);
+ * out[2] = columns per Y-step block, out[3] = 1 if it came from the process's tuning cache,
+ * out[4] = half-width of the H_rho1^{-1} stencil in the X-update, -1 for the separate solve. */
+tctf_status tctf_tuning(tctf_ctx* c, int32_t out[5]);
 
 /* Iterations run since create (or as restored). */
 tctf_status tctf_iterations(tctf_ctx* c, int64_t* iters);
@@ -223,8 +230,10 @@ tctf_status tctf_complete_noalloc(const tctf_params* p, const float* G, const ui
 /* Time one stage of the iteration: launch it `reps` times back to back on the context's
  * stream between two HIP events and return the mean duration in microseconds.  Stages:
  *   0 slice kernel (inverse tube transform, W-step, forward transform; the W~ stream)
- *   1 Z~ = X~Y~ products        2 A = W~Y~^* products and the X right-hand side
- *   3 tridiagonal H_rho1 solve
+ *   1 Z~ = X~Y~ products
+ *   2 A = W~Y~^* products and the X-update: the right-hand side, or with the H_rho1^{-1}
+ *     stencil (tctf_params.xsolve) the new X~ itself, written to a scratch buffer
+ *   3 tridiagonal H_rho1 solve (no launch where the stencil replaces it)
  *   4 X~^* W~ partials, with G_X, its pseudo-inverse and I - eta P_X
  *   5 Y-step and the column-block partials of G_Y
  *   6 G_Y from its partials, its pseudo-inverse and I - eta P_Y

@@ -24,7 +24,7 @@ class tctf_params(ctypes.Structure):
                 ("mu", ctypes.c_double), ("rho1", ctypes.c_double), ("rho2", ctypes.c_double),
                 ("eta", ctypes.c_double), ("precision", ctypes.c_int32), ("pinv_mode", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("rank_tol", ctypes.c_double), ("rank_every", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("xsolve", ctypes.c_int32)]
 
 
 class TctfError(RuntimeError):
@@ -177,7 +177,7 @@ def tctf_rank_vector(ctx, nb: int) -> list:
 
 
 def tctf_tuning(ctx) -> tuple:
-    v = (ctypes.c_int32 * 4)()
+    v = (ctypes.c_int32 * 5)()
     _check(library().tctf_tuning(ctx, v), "tctf_tuning")
     return tuple(v)
 
@@ -267,7 +267,7 @@ def tctf_last_error() -> str:
 # ---------------------------------------------------------------- torch convenience layer
 
 def make_params(n1, n2, n3, r, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision="fp32", pinv_mode=0,
-                eps=1e-6, rank_tol=0.0, rank_every=0, autotune=False) -> tctf_params:
+                eps=1e-6, rank_tol=0.0, rank_every=0, autotune=False, xsolve=0) -> tctf_params:
     p = tctf_default_params()
     p.n1, p.n2, p.n3, p.r = int(n1), int(n2), int(n3), int(r)
     p.mu, p.rho1, p.rho2, p.eta = float(mu), float(rho1), float(rho2), float(eta)
@@ -278,6 +278,7 @@ def make_params(n1, n2, n3, r, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision
     p.rank_tol = float(rank_tol)
     p.rank_every = int(rank_every)
     p.autotune = 1 if autotune else 0
+    p.xsolve = int(xsolve)
     return p
 
 
@@ -306,7 +307,7 @@ class Completion:
 
     def __init__(self, G, omega, r, *, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision="fp32",
                  pinv_mode=0, eps=1e-6, X0=None, Y0=None, seed=0, stream=None, rank_tol=0.0, rank_every=0,
-                 autotune=False):
+                 autotune=False, xsolve=0):
         import torch
         self._owned = True
         if not (G.is_cuda and omega.is_cuda):
@@ -318,7 +319,7 @@ class Completion:
         self.X0 = None if X0 is None else X0.contiguous().to(torch.float32)
         self.Y0 = None if Y0 is None else Y0.contiguous().to(torch.float32)
         self.params = make_params(n1, n2, n3, r, mu, rho1, rho2, eta, precision, pinv_mode, eps, rank_tol,
-                                  rank_every, autotune)
+                                  rank_every, autotune, xsolve)
         self.shape = (n1, n2, n3)
         self.r = r
         self.stream = stream
@@ -367,7 +368,8 @@ class Completion:
         return tctf_stationarity(self.ctx)
 
     def tuning(self):
-        """(slice path, columns per X~^* W~ block, columns per Y-step block, from the cache)."""
+        """(slice path, columns per X~^* W~ block, columns per Y-step block, from the cache,
+        half-width of the H_rho1^{-1} stencil in the X-update or -1 for the separate solve)."""
         return tctf_tuning(self.ctx)
 
     def rank_vector(self):

@@ -72,6 +72,7 @@ static int default_bcg(int n2, int nb, int r) {
 // depth of steps 3, 4 and 7), the columns per X~^* W~ block and per Y-step block.
 struct Knobs {
   int spath, bcg, ycw;
+  int hstencil;   // 1: the X-update applies H_rho1^{-1} as a stencil where hinv_stencil allows
 };
 #define TUNE_MIN_YCW 8
 
@@ -82,6 +83,7 @@ static Knobs default_knobs(const tctf_params& p) {
   k.spath = tctf::slice_default_path(p.n2, p.n3);
   k.bcg = default_bcg(p.n2, nb, p.r);
   tctf::ystep_split(p.n2, p.r, nb, &ny, &k.ycw);
+  k.hstencil = p.xsolve == 0;
   return k;
 }
 
@@ -190,6 +192,7 @@ static tctf_status validate(const tctf_params* p) {
   if (!(std::isfinite(p->rank_tol) && p->rank_tol >= 0.0)) return fail(TCTF_E_ARG, "rank_tol must be finite and >= 0");
   if (p->autotune != 0 && p->autotune != 1) return fail(TCTF_E_ARG, "autotune must be 0 or 1");
   if (p->rank_every < 0) return fail(TCTF_E_ARG, "rank_every must be >= 0");
+  if (p->xsolve != 0 && p->xsolve != 1) return fail(TCTF_E_ARG, "xsolve must be 0 or 1");
   return TCTF_OK;
 }
 
@@ -235,6 +238,7 @@ static void fill_plan(tctf_ctx* c, hipStream_t stream) {
   q.rho1 = p.rho1;
   q.rho2 = p.rho2;
   q.eta = p.eta;
+  q.hk = c->knobs.hstencil ? tctf::hinv_stencil(q.rho1, q.n1, q.r, q.htap) : -1;
   q.mixed = p.precision == TCTF_MIXED_BF16;
   q.force_eigen = p.pinv_mode == 1;
   q.stream = stream;
@@ -308,7 +312,7 @@ static tctf_status enqueue_iteration(tctf_ctx* c) {
   const Plan& p = c->plan;
   tctf_status s = TCTF_OK;
   if (s == TCTF_OK) s = stage(c, 2, [&] { tctf::launch_agemm(p, 0, 1); });
-  if (s == TCTF_OK) s = stage(c, 3, [&] { tctf::launch_hsolve(p); });
+  if (s == TCTF_OK && p.hk < 0) s = stage(c, 3, [&] { tctf::launch_hsolve(p); });   // else inside the X-update
   if (s == TCTF_OK && c->capturing) {
     // G_X, its pseudo-inverse and I - eta P_X are needed first by the Y-step: in the graph they
     // form a branch that runs beside the X~^* W~ chunk products and joins before the Y-step
@@ -431,10 +435,10 @@ static tctf_status enqueue_iteration(tctf_ctx* c);
 // path) and two tile shapes (rows per X~^* W~ chunk, columns per Y-step block), chosen per
 // problem shape by timing and kept for the process (per device).
 static std::mutex g_tune_mu;
-static std::map<std::array<int, 6>, Knobs> g_tune_cache;
+static std::map<std::array<int, 7>, Knobs> g_tune_cache;
 
-static std::array<int, 6> tune_key(const tctf_params& p, int device) {
-  return {p.n1, p.n2, p.n3, p.r, p.precision, device};
+static std::array<int, 7> tune_key(const tctf_params& p, int device) {
+  return {p.n1, p.n2, p.n3, p.r, p.precision, p.xsolve, device};
 }
 
 // Mean duration of one iteration over `reps` eager iterations after `warm`, from HIP events
@@ -492,12 +496,16 @@ static tctf_status autotune(tctf_ctx* c, const tctf_params* prm, const float* G,
     }
   };
   for (int path : {tctf::SPATH_COOP, tctf::SPATH_THREAD, tctf::SPATH_SPLIT})
-    if (path != best.spath && tctf::slice_path_valid(path, prm->n2, prm->n3)) trial({path, best.bcg, best.ycw});
+    if (path != best.spath && tctf::slice_path_valid(path, prm->n2, prm->n3))
+      trial({path, best.bcg, best.ycw, best.hstencil});
   for (int bcg : {16, 32})
-    if (bcg != best.bcg && tctf::bgemm_cols_valid(prm->r, bcg)) trial({best.spath, bcg, best.ycw});
+    if (bcg != best.bcg && tctf::bgemm_cols_valid(prm->r, bcg)) trial({best.spath, bcg, best.ycw, best.hstencil});
   const int ymax = 512 / prm->r < prm->n2 ? 512 / prm->r : prm->n2;   // the Y-step block holds r x ycw <= 512
   for (int ycw : {8, 16, 32, 64, ymax})
-    if (ycw != best.ycw && ycw >= TUNE_MIN_YCW && ycw <= ymax) trial({best.spath, best.bcg, ycw});
+    if (ycw != best.ycw && ycw >= TUNE_MIN_YCW && ycw <= ymax) trial({best.spath, best.bcg, ycw, best.hstencil});
+  double tap[2 * HINV_KMAX + 2];
+  if (best.hstencil && tctf::hinv_stencil(prm->rho1, prm->n1, prm->r, tap) >= 0)
+    trial({best.spath, best.bcg, best.ycw, 0});
   if (s != TCTF_OK) return s;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -506,12 +514,13 @@ static tctf_status autotune(tctf_ctx* c, const tctf_params* prm, const float* G,
   return ctx_init(c, prm, G, omega, X0, Y0, seed, ws, ws_bytes, stream, &best);
 }
 
-tctf_status tctf_tuning(tctf_ctx* c, int32_t out[4]) {
+tctf_status tctf_tuning(tctf_ctx* c, int32_t out[5]) {
   if (!c || !out) return fail(TCTF_E_ARG, "NULL argument");
   out[0] = c->knobs.spath;
   out[1] = c->knobs.bcg;
   out[2] = c->knobs.ycw;
   out[3] = c->tuned_from_cache;
+  out[4] = c->plan.hk;
   return TCTF_OK;
 }
 
@@ -896,8 +905,8 @@ tctf_status tctf_time_stage(tctf_ctx* c, int32_t stage, int32_t reps, double* me
     switch (stage) {
       case 0: tctf::launch_slice(p, tctf::SLICE_ITER, nullptr, nullptr, 0); break;
       case 1: tctf::launch_zgemm(p); break;
-      case 2: tctf::launch_agemm(p); break;
-      case 3: tctf::launch_hsolve(p); break;
+      case 2: tctf::launch_agemm(p, 0, 0, 1); break;
+      case 3: if (p.hk < 0) tctf::launch_hsolve(p); break;
       case 4: tctf::launch_gramx(p); tctf::launch_bgemm(p); break;
       case 5: tctf::launch_ystep(p, 1); break;
       case 6: tctf::launch_pinvy(p, p.stream); break;

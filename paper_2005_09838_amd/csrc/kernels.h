@@ -6,6 +6,8 @@
 
 namespace tctf {
 
+#define HINV_KMAX 12   // widest stencil of H_rho1^{-1} applied inside the X-update
+
 // Device buffers and sizes of one completion (carved from the caller's workspace).
 struct Plan {
   int n1, n2, n3, r, nb;       // nb = n3/2 + 1 stored frequencies
@@ -14,6 +16,10 @@ struct Plan {
   int spath;                   // slice path: SPATH_COOP, SPATH_THREAD or SPATH_SPLIT
   int ncu;                     // compute units of the device
   double mu, rho1, rho2, eta;
+  // H_rho1^{-1} as a stencil of half-width hk inside the X-update (k_agemm), hk = -1: the
+  // X-update forms the right-hand side and k_hsolve solves (see hinv_stencil)
+  int hk;
+  double htap[2 * HINV_KMAX + 2];
   int mixed, force_eigen;
   hipStream_t stream;
 
@@ -90,7 +96,12 @@ bool slice_hosts_pinvy(const Plan& p);   // the iteration's slice launch also fo
 size_t slice_launch_lds_bytes(const Plan& p);
 void launch_slice(const Plan& p, int mode, float* w_out, float* z_out, int w_from_g);
 void launch_zgemm(const Plan& p, int with_pinv = 0);   // with_pinv: also G_Y^+ (pinvy_block)
-void launch_agemm(const Plan& p, int raw_a = 0, int advance = 0);   // advance: next rounding-bit counter
+// advance: next rounding-bit counter; scratch_out: with the stencil, X~ goes to the rhs
+// buffer instead of X~ itself (a stage timing that leaves the state as it was)
+void launch_agemm(const Plan& p, int raw_a = 0, int advance = 0, int scratch_out = 0);
+// Half-width k and taps c lambda^d (d = 0 .. 2k + 1) of H_rho1^{-1} as a stencil, or -1
+// where the stencil would be wider than HINV_KMAX, r > 16 or n1 < 2k + 2
+int hinv_stencil(double rho1, int n1, int r, double* tap);
 void launch_hsolve(const Plan& p);
 void launch_bgemm(const Plan& p);   // X~^* W~ over all rows
 void launch_gramx(const Plan& p);   // G_X, (H X~)^*(H X~), G_X^+ and I - eta P_X

@@ -293,23 +293,43 @@ void launch_zgemm(const Plan& p, int with_pinv) {
 // consecutive floats W'[m][16 g + 4 q ..] (two complex entries of W~), and the matching
 // Y' values are the same two complex entries of Y~ row s (with the sign pattern).
 // Block: 64 rows x one frequency, 4 wavefronts of 16 rows, up to AG_COLS columns of W~ per
-// pass with every W~ load of the pass issued before the products.  The epilogue forms, in
-// FP64, R(i, :) = eta A(i, :) G_Y^+ + (H_rho1 U)(i, :), U = X~ (I - eta P_Y) (U only when
-// I - eta P_Y is not exactly 0).
+// pass with every W~ load of the pass issued before the products.
+// Epilogue, in FP64, with U = X~ (I - eta P_Y) (U = 0 when I - eta P_Y is exactly 0):
+// * hk >= 0: the whole X-update.  Since X~_new = H_rho1^{-1} (eta A G_Y^+ + H_rho1 U) =
+//   U + eta H_rho1^{-1} V with V = A G_Y^+, and H_rho1^{-1} is the stencil of hinv_stencil,
+//   the block forms V on its 64 rows (zero outside the matrix) and writes X~_new on the
+//   64 - 2 hk rows whose stencil lies inside them; consecutive blocks overlap by 2 hk rows.
+//   U needs X~ on the output rows only, which no other block writes, so X~ is updated in
+//   place.  Real bins (b = 0, n3 / 2) keep a zero imaginary part.
+// * hk = -1: the right-hand side R = eta A G_Y^+ + H_rho1 U for k_hsolve.
 #define AG_ROWS 64
 #define AG_COLS 128
+struct HStencil {
+  int k;                            // half-width, -1: right-hand side only
+  double tap[2 * HINV_KMAX + 2];    // c lambda^d
+};
 template <int RM, bool MIXED>   // r <= RM; MIXED: W~ stored as packed bf16 pairs
 __global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __restrict__ yt,
-                                               const float2* __restrict__ xt, const cd* __restrict__ gyp,
+                                               const float2* xt, const cd* __restrict__ gyp,   // xt may be xout
                                                const cd* __restrict__ qy, const int* __restrict__ qy_zero,
                                                float2* __restrict__ rhs, int n1, int n2, int r, int nb,
-                                               double eta, double rho1, int raw_a, uint32_t* ctr) {
+                                               double eta, double rho1, int raw_a, uint32_t* ctr,
+                                               float2* xout, int n3, HStencil hs) {
   __shared__ __align__(16) float2 ysh[RM * AG_COLS];   // [s][j] of the column chunk (MIXED: split words)
   __shared__ __align__(16) float2 ash[AG_ROWS * RM];   // A rows, then the results
   __shared__ __align__(16) cd gs[RM * RM];             // G_Y^+
-  const int i0 = blockIdx.x * AG_ROWS, b = blockIdx.y, tid = threadIdx.x;
+  __shared__ __align__(16) cd vsh[RM <= 16 ? AG_ROWS * RM : 1];   // V = A G_Y^+ [s][row] (stencil only)
+  __shared__ double tsh[2 * HINV_KMAX + 2];                        // the stencil's taps
+  const int hk = (RM <= 16 && !raw_a) ? hs.k : -1;
+#pragma unroll
+  for (int d = 0; d < 2 * HINV_KMAX + 2; ++d)   // constant indices: the taps stay in the argument segment
+    if ((int)threadIdx.x == d && d <= 2 * hk + 1) tsh[d] = hs.tap[d];   // read after the first barrier
+  // with the stencil, block x covers rows x (64 - 2 hk) - hk .. + 63 (some outside the matrix)
+  const int i0 = hk >= 0 ? (int)blockIdx.x * (AG_ROWS - 2 * hk) - hk : (int)blockIdx.x * AG_ROWS;
+  const int b = blockIdx.y, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, m = lane & 15, q = lane >> 4;
   const int row = i0 + 16 * w + m;
+  const bool row_in = row >= 0 && row < n1;
   // one thread of the launch advances the counter of the rounding bits that this
   // iteration's slice kernel (a later launch) uses for the BF16 W~
   if (ctr && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) ctr[0] += 1u;
@@ -336,7 +356,7 @@ __global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __r
     // group g covers columns j0 + 8 g .. + 7; this lane takes 2 (groups past the last valid
     // one load the last one again: no extra memory traffic, the values are dropped)
     raw_t lo[AG_COLS / 8], hi[AG_COLS / 8];
-    const raw_t* wrow = (const raw_t*)wt + ((size_t)min(row, n1 - 1) * nb + b) * n2 + j0 + 2 * q;
+    const raw_t* wrow = (const raw_t*)wt + ((size_t)min(max(row, 0), n1 - 1) * nb + b) * n2 + j0 + 2 * q;
 #pragma unroll
     for (int g = 0; g < AG_COLS / 8; ++g) {
       const int gc = min(g, ngroups - 1);
@@ -355,7 +375,7 @@ __global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __r
 #pragma unroll
     for (int g = 0; g < AG_COLS / 8; ++g) {
       if (g < ngroups) {
-        const int valid = row < n1 ? min(2, nc - (8 * g + 2 * q)) : 0;
+        const int valid = row_in ? min(2, nc - (8 * g + 2 * q)) : 0;
         if constexpr (MIXED) {
           // BF16 matrix cores: this lane's four K values are the two packed W~ words as they
           // are (exact), Y~ enters split into its hi and lo BF16 parts (two products)
@@ -425,9 +445,72 @@ __global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __r
     if (!noqy) qs[e] = qy[(size_t)b * r * r + e];
   }
   __syncthreads();
-  // thread (il, qq) = (tid / 4, tid % 4) forms R(i0 + il, s) for s = qq, qq + 4, ...
+  // thread (il, qq) = (tid / 4, tid % 4) takes row i0 + il, columns s = qq, qq + 4, ...
   const int il = tid >> 2, qq = tid & 3, i = i0 + il;
   constexpr int SP = RM / 4;
+  if (hk >= 0) {
+    {
+      cd ag[SP];   // V(i, :) = A(i, :) G_Y^+, one independent chain per column
+#pragma unroll
+      for (int us = 0; us < SP; ++us) ag[us] = cd_make(0.0, 0.0);
+      if (i >= 0 && i < n1) {
+        for (int u = 0; u < r; ++u) {
+          const float2 av = ash[il * r + u];
+          const cd a = cd_make(av.x, av.y);
+#pragma unroll
+          for (int us = 0; us < SP; ++us) cd_fma(ag[us], a, gs[u * r + min(qq + 4 * us, r - 1)]);
+        }
+      }
+#pragma unroll
+      for (int us = 0; us < SP; ++us)
+        if (qq + 4 * us < r) vsh[(qq + 4 * us) * AG_ROWS + il] = ag[us];
+    }
+    __syncthreads();   // V of every row of the block is in LDS
+    // thread (ro, sg) = (tid % 64, tid / 64): row i0 + ro, columns s = sg, sg + 4, ...
+    const int ro = tid & 63, sg = tid >> 6, io = i0 + ro;
+    const bool out = io >= 0 && io < n1 && ro >= hk && ro < AG_ROWS - hk;
+    cd t[SP];
+#pragma unroll
+    for (int us = 0; us < SP; ++us) t[us] = cd_make(0.0, 0.0);
+    if (out) {
+      // (H_rho1^{-1} V)(io, s): direct tap c lambda^|io - j| plus the reflections in the two
+      // ends, c lambda^(io + j + 1) and c lambda^(2 n1 - 1 - io - j), where within the table
+      const int tmax = 2 * hk + 1;
+      for (int d = -hk; d <= hk; ++d) {
+        const int j = io + d;
+        if (j < 0 || j >= n1) continue;
+        const int e1 = io + j + 1, e2 = 2 * n1 - 1 - io - j;
+        const double wgt = tsh[d < 0 ? -d : d] + (e1 <= tmax ? tsh[min(e1, tmax)] : 0.0) +
+                           (e2 <= tmax ? tsh[min(e2, tmax)] : 0.0);
+#pragma unroll
+        for (int us = 0; us < SP; ++us) {
+          const cd v = vsh[min(sg + 4 * us, r - 1) * AG_ROWS + ro + d];
+          t[us].re = fma(wgt, v.re, t[us].re);
+          t[us].im = fma(wgt, v.im, t[us].im);
+        }
+      }
+#pragma unroll
+      for (int us = 0; us < SP; ++us) t[us] = cd_scale(t[us], eta);
+      if (!noqy) {
+        for (int v2 = 0; v2 < r; ++v2) {
+          const float2 x0 = xt[((size_t)b * r + v2) * n1 + io];
+          const cd xv = cd_make(x0.x, x0.y);
+#pragma unroll
+          for (int us = 0; us < SP; ++us) cd_fma(t[us], xv, qs[v2 * r + min(sg + 4 * us, r - 1)]);
+        }
+      }
+    }
+    __syncthreads();   // every X~ read of the block is done before X~ is overwritten
+    if (out) {
+      const bool real_bin = bin_is_real(b, n3);
+#pragma unroll
+      for (int us = 0; us < SP; ++us) {
+        const int s = sg + 4 * us;
+        if (s < r) xout[((size_t)b * r + s) * n1 + io] = make_float2((float)t[us].re, real_bin ? 0.0f : (float)t[us].im);
+      }
+    }
+    return;
+  }
   float2 res[SP];
   if (i < n1) {
     const double deg = (n1 == 1) ? 0.0 : ((i == 0 || i == n1 - 1) ? 1.0 : 2.0);
@@ -482,11 +565,49 @@ __global__ void __launch_bounds__(256) k_agemm(const void* wt, const float2* __r
   }
 }
 
-void launch_agemm(const Plan& p, int raw_a, int advance) {
-  dim3 grid((p.n1 + AG_ROWS - 1) / AG_ROWS, p.nb);
+// H_rho1 = I + rho1 D^T D (D: first differences along mode 1) is tridiagonal with
+// diagonal 1 + 2 rho1 (1 + rho1 in the end rows) and off-diagonal -rho1.  Away from the
+// ends its inverse is c lambda^|i - j|, lambda the root in (0, 1) of
+// rho1 lambda^2 - (1 + 2 rho1) lambda + rho1 = 0 and c = lambda / (rho1 (1 - lambda^2));
+// an end row is a mirror (the row equation holds with a ghost entry equal to the end
+// entry), which adds the image terms c lambda^(i + j + 1) and c lambda^(2 n1 - 1 - i - j).
+// The images of images are below lambda^(2 n1), and dropping every tap with |i - j| > k
+// changes a result by at most c lambda^(k + 1) / (1 - lambda) times the largest |V| there:
+// k is the least with lambda^(k + 1) <= 2^-40: below FP32's rounding unit even where
+// neighbouring rows differ in scale by 10^4 (k = 5 at rho1 = 0.01, 11 at rho1 = 0.1).
+int hinv_stencil(double rho1, int n1, int r, double* tap) {
+  if (r > 16 || !(rho1 >= 0.0)) return -1;
+  double lam = 0.0, c = 1.0;
+  if (rho1 > 0.0) {
+    const double a = 1.0 + 2.0 * rho1;
+    lam = 2.0 * rho1 / (a + sqrt(a * a - 4.0 * rho1 * rho1));   // the small root, without cancellation
+    c = lam / (rho1 * (1.0 - lam * lam));
+  }
+  int k = 0;
+  double p = lam;   // lambda^(k + 1)
+  while (p > 0x1p-40 && k <= HINV_KMAX) {
+    p *= lam;
+    ++k;
+  }
+  if (k > HINV_KMAX || n1 < 2 * k + 2) return -1;
+  double v = c;
+  for (int d = 0; d <= 2 * k + 1; ++d) {
+    tap[d] = v;
+    v *= lam;
+  }
+  return k;
+}
+
+void launch_agemm(const Plan& p, int raw_a, int advance, int scratch_out) {
+  HStencil hs;
+  hs.k = raw_a ? -1 : p.hk;
+  for (int d = 0; d < 2 * HINV_KMAX + 2; ++d) hs.tap[d] = d <= 2 * hs.k + 1 ? p.htap[d] : 0.0;
+  const int rows = hs.k >= 0 ? AG_ROWS - 2 * hs.k : AG_ROWS;
+  float2* xout = scratch_out ? p.rhs : p.xt;
+  dim3 grid((p.n1 + rows - 1) / rows, p.nb);
 #define TCTF_AGEMM(RM, MX)                                                                                    \
   k_agemm<RM, MX><<<grid, 256, 0, p.stream>>>(p.wt, p.yt, p.xt, p.gyp, p.qy, p.qy_zero, p.rhs, p.n1, p.n2, p.r, \
-                                              p.nb, p.eta, p.rho1, raw_a, advance ? p.ctr : nullptr)
+                                              p.nb, p.eta, p.rho1, raw_a, advance ? p.ctr : nullptr, xout, p.n3, hs)
   if (p.mixed) {
     if (p.r <= 8) TCTF_AGEMM(8, true);
     else if (p.r <= 16) TCTF_AGEMM(16, true);

@@ -25,12 +25,14 @@ def to_dev(a):
 
 
 def gpu_run(d, r, iters, *, mu=1e-2, rho1=1e-2, rho2=1e-2, eta=1.0, precision="fp32", pinv_mode=0,
-            history=False, want=("W", "Z"), x0=True, y0=True, seed=0, track=False, rank_tol=0.0, rank_every=0):
+            history=False, want=("W", "Z"), x0=True, y0=True, seed=0, track=False, rank_tol=0.0, rank_every=0,
+            xsolve=0):
     """Run the HIP path; returns dict with requested results and the f0 history."""
     from paper_2005_09838_amd import Completion
     c = Completion(to_dev(d["G"]), to_dev(d["omega"]), r, mu=mu, rho1=rho1, rho2=rho2, eta=eta,
                    precision=precision, pinv_mode=pinv_mode, X0=to_dev(d["X0"]) if x0 else None,
-                   Y0=to_dev(d["Y0"]) if y0 else None, seed=seed, rank_tol=rank_tol, rank_every=rank_every)
+                   Y0=to_dev(d["Y0"]) if y0 else None, seed=seed, rank_tol=rank_tol, rank_every=rank_every,
+                   xsolve=xsolve)
     if track:
         c.track_termination(True)
     f = [c.objective()] if history else []

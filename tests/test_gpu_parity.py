@@ -100,6 +100,27 @@ def test_sampling_extremes(p):
         assert np.array_equal(g["W"], d["G"].astype(np.float64))
 
 
+@pytest.mark.parametrize("n1,n2,n3,r,rho1,eta", [
+    (300, 40, 12, 6, 1e-2, 1.0),   # stencil half-width 5, five row blocks per frequency
+    (300, 40, 12, 6, 0.1, 0.7),    # half-width 11 with the X~ (I - eta P_Y) term; Nyquist bin
+    (12, 20, 8, 3, 1e-2, 0.6),     # n1 = 2 k + 2: one block, both mirror ends in every stencil
+    (90, 30, 7, 16, 0.0, 1.0),     # rho1 = 0: H_rho1 = I, half-width 0; r = 16
+])
+def test_x_update_stencil_and_separate_solve(n1, n2, n3, r, rho1, eta):
+    """The X-update with H_rho1^{-1} applied as a stencil inside the A = W~ Y~^* launch and with
+    the separate tridiagonal solve: each against the oracle, and the two within FP32 rounding."""
+    d = make_inputs(n1, n2, n3, r, p=0.4, seed=n1 + r, sigma_od=1.5)
+    a = gpu_run(d, r, 6, rho1=rho1, eta=eta)
+    b = gpu_run(d, r, 6, rho1=rho1, eta=eta, xsolve=1)
+    ka, kb = a["ctx"].tuning()[4], b["ctx"].tuning()[4]
+    print(f"{n1}x{n2}x{n3} r{r} rho1 {rho1}: half-width {ka} / {kb}, W rel {rel(a['W'], b['W']):.2e}", flush=True)
+    assert ka >= 0 and kb == -1
+    st, info = oracle_run(d, r, 6, rho1=rho1, eta=eta, history=True)
+    _compare(a, st, info, label=f"stencil k={ka}")
+    _compare(b, st, info, label="separate solve")
+    assert rel(a["W"], b["W"]) < 2e-6
+
+
 def test_exact_recovery_in_one_sweep():
     """Fully observed exact tubal rank r with rho1 = 0: Z = G after one iteration."""
     rng = np.random.default_rng(4)
