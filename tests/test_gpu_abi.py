@@ -153,6 +153,35 @@ def test_stage_profile_records_each_launch():
     assert np.array_equal(c.result()["W"].cpu().numpy(), a["W"].astype(np.float32))
 
 
+@pytest.mark.parametrize("xsolve", [0, 1])
+def test_stage_timing_leaves_the_iterate_unchanged(xsolve):
+    """tctf_time_stage recomputes stages 0-6 from the current state without advancing it:
+    the iterations after it give the same bits as a context that was never timed (with the
+    X-update's H_rho1^{-1} stencil, stage 2 writes the new X~ to a scratch buffer)."""
+    d = make_inputs(70, 40, 12, 6, p=0.4, seed=21)
+    a = gpu_run(d, 6, 9, xsolve=xsolve)
+    b = gpu_run(d, 6, 4, xsolve=xsolve)
+    c = b["ctx"]
+    assert (c.tuning()[4] >= 0) == (xsolve == 0)
+    for st in range(7):
+        assert c.time_stage(st, reps=3) > 0.0
+    c.step(5)
+    assert np.array_equal(c.result()["W"].cpu().numpy(), a["W"].astype(np.float32))
+    assert c.objective() == a["ctx"].objective()
+
+
+def test_mixed_precision_stencil_and_separate_solve():
+    """Mixed precision with the H_rho1^{-1} stencil in the X-update and with the separate
+    tridiagonal solve: the two stay within the mixed mode's own noise of each other."""
+    w, d = make_workload("od144x288x28_r8_p40")
+    a = gpu_run(d, w.r, 20, precision="mixed")
+    b = gpu_run(d, w.r, 20, precision="mixed", xsolve=1)
+    assert a["ctx"].tuning()[4] >= 0 and b["ctx"].tuning()[4] == -1
+    e = rel(a["W"], b["W"])
+    print(f"mixed, stencil vs separate solve after 20 iterations: W rel {e:.2e}", flush=True)
+    assert e < 1e-2
+
+
 def test_graph_replays_match_eager_launches():
     """Blocks of iterations replayed from the captured graph give the same bits as eager
     launches, across several replays separated by eager work and synchronisations."""
