@@ -25,6 +25,13 @@
       dispatch (each MOPS unit is 512 flops), the rate over the kernel's mean duration from a
       kernel-trace run against the dense peak of its type, and the matrix-core busy share
       (busy cycles over that duration's cycles at 2.4 GHz times the chip's 1024 SIMDs).
+
+  python -m paper_2005_09838_amd.profile_summary timeline DIR --anchor NAME
+         --per-iteration PATTERN ... --title T --command CMD --out FILE
+      the kernels of one iteration in start order, from the *kernel_trace.csv of a
+      kernel-trace run: the windows between consecutive starts of the anchor kernel that
+      hold each PATTERN once (graph-replayed iterations), and per kernel the median start,
+      end and duration relative to the window's start, with the idle time before it.
 """
 from __future__ import annotations
 
@@ -226,6 +233,50 @@ def write_mfma(a) -> None:
         f.write("\n".join(lines) + "\n")
 
 
+def write_timeline(a) -> None:
+    path = glob.glob(os.path.join(a.directory, "**", "*kernel_trace.csv"), recursive=True)[0]
+    with open(path) as f:
+        rows = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in csv.DictReader(f)]
+    rows.sort()
+    starts = [i for i, r in enumerate(rows) if a.anchor in r[2]]
+    windows = []
+    for i0, i1 in zip(starts, starts[1:]):
+        ker = rows[i0:i1]
+        picked = []
+        for pat in a.per_iteration:
+            hits = [k for k in ker if pat in k[2]]
+            if len(hits) != 1:
+                break
+            picked.append(hits[0])
+        else:
+            if len(ker) == len(a.per_iteration):
+                windows.append((rows[i1][0] - rows[i0][0], rows[i0][0], picked))
+    if not windows:
+        raise SystemExit("no iteration window holds every pattern once")
+    period = statistics.median(w[0] for w in windows)
+    windows = [w for w in windows if abs(w[0] - period) <= 0.2 * period]
+    lines = [a.title, f"source_sha256: {source_digest()}",
+             f"iterations: {len(windows)} (graph-replayed windows between starts of {a.anchor})",
+             f"median period_us: {period / 1000:.2f}", "",
+             f"{'kernel':32s} {'start_us':>9s} {'end_us':>9s} {'dur_us':>8s} {'idle_before_us':>15s}"]
+    med = []
+    for j in range(len(a.per_iteration)):
+        st = statistics.median((w[2][j][0] - w[1]) / 1000 for w in windows)
+        en = statistics.median((w[2][j][1] - w[1]) / 1000 for w in windows)
+        med.append((st, en, _short(windows[0][2][j][2])))
+    med.sort()
+    busy_end = 0.0
+    for st, en, name in med:
+        lines.append(f"{name[:32]:32s} {st:9.2f} {en:9.2f} {en - st:8.2f} {max(0.0, st - busy_end):15.2f}")
+        busy_end = max(busy_end, en)
+    lines.append(f"{'(next iteration)':32s} {period / 1000:9.2f} {'':9s} {'':8s} "
+                 f"{max(0.0, period / 1000 - busy_end):15.2f}")
+    lines += ["", "idle_before_us: from the latest end among the earlier kernels to this start (0 when they overlap)",
+              "commands:"] + [f"  {c}" for c in a.command]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="what", required=True)
@@ -252,6 +303,12 @@ def main() -> None:
     for k in ("counters", "stats", "title", "out"):
         m.add_argument("--" + k, required=True)
     m.add_argument("--command", action="append", required=True)
+    tl = sub.add_parser("timeline")
+    tl.add_argument("directory")
+    for k in ("anchor", "title", "out"):
+        tl.add_argument("--" + k, required=True)
+    tl.add_argument("--per-iteration", nargs="+", required=True)
+    tl.add_argument("--command", action="append", required=True)
     a = ap.parse_args()
     if a.what == "stats":
         write_stats(a.directory, a.command, a.out)
@@ -259,6 +316,8 @@ def main() -> None:
         write_traffic(a)
     elif a.what == "all-traffic":
         write_all_traffic(a)
+    elif a.what == "timeline":
+        write_timeline(a)
     else:
         write_mfma(a)
 
