@@ -190,11 +190,12 @@ __host__ __device__ inline YLayout ystep_layout(int r, int cw) {
   return L;
 }
 
-// Column blocks of the Y-step: enough blocks to cover the compute units, at least 8 columns
-// each, at most 512 / r (two elements per thread).
+// Column blocks of the Y-step: enough blocks to cover the compute units, a multiple of 8
+// columns each (at least 8), at most 512 / r (two elements per thread).
 void ystep_split(int n2, int r, int nb, int* ny, int* cw) {
   const int want = (256 + nb - 1) / nb;
   int c = (n2 + want - 1) / want;
+  c &= ~7;   // so that every block starts on a 64-byte boundary of a row of Y~
   if (c < 8) c = 8;
   if (c > 512 / r) c = 512 / r;
   if (c > n2) c = n2;
