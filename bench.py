@@ -348,8 +348,8 @@ def main():
                     help="run one precision (no equal-error comparison); for counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs a completion on a single MI355X "
-              "(--gpus 1); multi-GPU runs are not part of it.", file=sys.stderr)
+        print("bench.py measures one GPU (--gpus 1): a completion runs on a single MI355X; "
+              "runs over several GPUs are not supported.", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

@@ -158,7 +158,7 @@ def iterate(prob: Problem, st: State, check_symmetry: bool = True) -> State:
 
 def rank_adjust(prob: Problem, st: State, tol: float):
     """Step 5 of the algorithm box (adjust the rank vector r^(l+1) and the sizes of X~_k,
-    Y~_k) under this build's rule, which the paper leaves open: in every frequency k keep the
+    Y~_k) by the following rule (the paper leaves the rule open): in every frequency k keep the
     components of Z~_k = X~_k Y~_k whose singular values exceed tol times the largest singular
     value over all frequencies.  With the SVD Z~_k = U S V^*, the kept part is written as
     X~_k = U_q S_q, Y~_k = V_q^* in the first q = r_k columns / rows, the rest zero (the factor
