@@ -105,6 +105,7 @@ def test_sampling_extremes(p):
     (300, 40, 12, 6, 0.1, 0.7),    # half-width 11 with the X~ (I - eta P_Y) term; Nyquist bin
     (12, 20, 8, 3, 1e-2, 0.6),     # n1 = 2 k + 2: one block, both mirror ends in every stencil
     (90, 30, 7, 16, 0.0, 1.0),     # rho1 = 0: H_rho1 = I, half-width 0; r = 16
+    (130, 20, 10, 16, 0.15, 0.8),  # the widest stencil, half-width 12: 40 output rows per block
 ])
 def test_x_update_stencil_and_separate_solve(n1, n2, n3, r, rho1, eta):
     """The X-update with H_rho1^{-1} applied as a stencil inside the A = W~ Y~^* launch and with
@@ -119,6 +120,17 @@ def test_x_update_stencil_and_separate_solve(n1, n2, n3, r, rho1, eta):
     _compare(a, st, info, label=f"stencil k={ka}")
     _compare(b, st, info, label="separate solve")
     assert rel(a["W"], b["W"]) < 2e-6
+
+
+@pytest.mark.parametrize("n1,rho1,expect", [(40, 0.16, -1), (40, 0.15, 12), (11, 0.01, -1), (12, 0.01, 5)])
+def test_x_update_form_follows_the_rule(n1, rho1, expect):
+    """The stencil is used up to half-width 12 and for n1 >= 2 k + 2 (else the tridiagonal
+    solve), and either way the run matches the oracle."""
+    d = make_inputs(n1, 24, 8, 4, p=0.4, seed=n1, sigma_od=1.5)
+    g = gpu_run(d, 4, 5, rho1=rho1)
+    assert g["ctx"].tuning()[4] == expect
+    st, info = oracle_run(d, 4, 5, rho1=rho1, history=True)
+    _compare(g, st, info, label=f"n1 {n1} rho1 {rho1} half-width {expect}")
 
 
 def test_exact_recovery_in_one_sweep():
